@@ -1,0 +1,213 @@
+"""Plain FP64 CPU oracle of the MRHS DD-alpha-AMG setup path (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The GPU library never imports or calls it,
+and the two share no code.  All arrays are numpy complex128 in the canonical
+layout: links [4][V][3][3], vectors [n_rhs][V][4][3] (component 3*spin + colour),
+site index x0 + L0*(x1 + L1*(x2 + L2*x3)).
+
+Every function cites the passage of the paper (Richtmann, Heybrock, Wettig,
+Lattice 2015) it follows; the Wilson-clover operator, SAP and MR are the
+standard definitions the paper cites but does not print (readings listed in
+oracle.c).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+
+def build(force=False):
+    """Compile oracle.c with plain gcc (no intrinsics, no fast-math)."""
+    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-std=gnu99", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        p, i, d, l = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_long
+        sig = {
+            "oracle_gamma": (i, [i, p]),
+            "oracle_clover": (None, [p, p, d, d, p]),
+            "oracle_dirac": (None, [p, p, p, p, p, i]),
+            "oracle_block_dirac": (None, [p, p, p, p, p, p, i]),
+            "oracle_mr": (None, [p, p, p, p, l, p, i, p, p]),
+            "oracle_sap": (i, [p, p, p, p, p, p, i, i, i]),
+            "oracle_residual_norms": (None, [p, p, p, p, p, i, p]),
+            "oracle_block_gs": (i, [p, p, p, i, p, p]),
+            "oracle_restrict": (None, [p, p, p, i, p, p, i]),
+            "oracle_prolong": (None, [p, p, p, i, p, p, i]),
+            "oracle_coarse_op": (None, [p, p, p, p, p, i, p, p, l]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _ext(L):
+    return np.ascontiguousarray(L, dtype=np.int32)
+
+
+def _c128(a):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def volume(L):
+    return int(np.prod(L))
+
+
+def gamma(mu):
+    """g_mu (mu = 0..3, DeGrand-Rossi chiral basis) or g5 = g0 g1 g2 g3 (mu = 4)."""
+    out = np.zeros((4, 4), np.complex128)
+    if lib().oracle_gamma(mu, _ptr(out)) != 0:
+        raise ValueError(mu)
+    return out
+
+
+def clover(L, U, csw, m0):
+    """A(x) = (4 + m0) + C(x) per site, [V][12][12] (the Dirac operator of Sec. 2's 12V vectors)."""
+    L = _ext(L)
+    U = _c128(U)
+    A = np.zeros((volume(L), 12, 12), np.complex128)
+    lib().oracle_clover(_ptr(L), _ptr(U), float(csw), float(m0), _ptr(A))
+    return A
+
+
+def _vecs(x, L):
+    x = _c128(x)
+    V = volume(L)
+    n = x.size // (12 * V)
+    if x.size != n * 12 * V:
+        raise ValueError("vector size is not a multiple of 12 V")
+    return x, n
+
+
+def dirac(L, U, A, x):
+    """y = D x for a stack of vectors [n][V][4][3]."""
+    L = _ext(L)
+    x, n = _vecs(x, L)
+    y = np.zeros_like(x)
+    lib().oracle_dirac(_ptr(L), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(x), _ptr(y), n)
+    return y
+
+
+def block_dirac(L, b, U, A, x):
+    """y = sum_j I_j D_j I_j^T x: D with hops between different blocks dropped."""
+    L, b = _ext(L), _ext(b)
+    x, n = _vecs(x, L)
+    y = np.zeros_like(x)
+    lib().oracle_block_dirac(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(x), _ptr(y), n)
+    return y
+
+
+def mr(L, b, U, A, j, r, n_mr):
+    """Minimal residual on block j for one full-lattice residual r: returns (e, ||rho|| history)."""
+    L, b = _ext(L), _ext(b)
+    r, n = _vecs(r, L)
+    assert n == 1
+    e = np.zeros_like(r)
+    norms = np.zeros(n_mr + 1)
+    lib().oracle_mr(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), int(j), _ptr(r), int(n_mr), _ptr(e), _ptr(norms))
+    return e, norms
+
+
+def sap(L, b, U, A, rhs, n_sap, n_mr):
+    """x = SAP(rhs) from a zero start (the initial setup phase of Sec. 2), per vector."""
+    L, b = _ext(L), _ext(b)
+    rhs, n = _vecs(rhs, L)
+    x = np.zeros_like(rhs)
+    rc = lib().oracle_sap(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(rhs), _ptr(x), n, int(n_sap), int(n_mr))
+    if rc != 0:
+        raise ValueError("oracle_sap: bad geometry")
+    return x
+
+
+def residual_norms(L, U, A, rhs, x):
+    """||b_k - D x_k|| / ||b_k|| per vector."""
+    L = _ext(L)
+    rhs, n = _vecs(rhs, L)
+    x, n2 = _vecs(x, L)
+    assert n == n2
+    out = np.zeros(n)
+    lib().oracle_residual_norms(_ptr(L), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(rhs), _ptr(x), n, _ptr(out))
+    return out
+
+
+def n_aggregates(L, a):
+    return volume([L[m] // a[m] for m in range(4)])
+
+
+def block_gs(L, a, V, return_T=False):
+    """Per aggregate and spin half: V^h_i = Q^h_i T^h_i (setup of R, P = R^dag; Sec. 2, Alg. 3).
+
+    Returns Q (same shape as V) [and T [n_agg][2][n_tv][n_tv]]; raises on rank deficiency."""
+    L, a = _ext(L), _ext(a)
+    V, n_tv = _vecs(V, L)
+    Q = np.zeros_like(V)
+    T = np.zeros((n_aggregates(L, a), 2, n_tv, n_tv), np.complex128)
+    rc = lib().oracle_block_gs(_ptr(L), _ptr(a), _ptr(V), n_tv, _ptr(Q), _ptr(T))
+    if rc < 0:
+        raise ValueError("oracle_block_gs: bad geometry")
+    if rc > 0:
+        raise np.linalg.LinAlgError("rank-deficient aggregate half %d" % (rc - 1))
+    return (Q, T) if return_T else Q
+
+
+def restrict(L, a, Q, y):
+    """y_c = R y, R = Q^dag per aggregate half (Alg. 3)."""
+    L, a = _ext(L), _ext(a)
+    Q, n_tv = _vecs(Q, L)
+    y, n = _vecs(y, L)
+    yc = np.zeros((n, n_aggregates(L, a), 2, n_tv), np.complex128)
+    lib().oracle_restrict(_ptr(L), _ptr(a), _ptr(Q), n_tv, _ptr(y), _ptr(yc), n)
+    return yc
+
+
+def prolong(L, a, Q, yc):
+    """y = P y_c, P = Q (Sec. 2: P = R^dag)."""
+    L, a = _ext(L), _ext(a)
+    Q, n_tv = _vecs(Q, L)
+    yc = _c128(yc)
+    n = yc.size // (n_aggregates(L, a) * 2 * n_tv)
+    y = np.zeros((n, volume(L), 4, 3), np.complex128)
+    lib().oracle_prolong(_ptr(L), _ptr(a), _ptr(Q), n_tv, _ptr(yc), _ptr(y), n)
+    return y
+
+
+def coarse_op(L, a, U, A, Q, agg_list=None):
+    """D_c = R D P as 9 blocks per coarse site [self,+x,+y,+z,+t,-x,-y,-z,-t], each
+    2 n_tv x 2 n_tv (Sec. 2: coarse-grid operator from the test vectors)."""
+    L, a = _ext(L), _ext(a)
+    Q, n_tv = _vecs(Q, L)
+    nc = 2 * n_tv
+    Dc = np.zeros((n_aggregates(L, a), 9, nc, nc), np.complex128)
+    if agg_list is None:
+        lst, nl = None, 0
+    else:
+        lst = np.ascontiguousarray(agg_list, dtype=np.int64)
+        nl = lst.size
+    lib().oracle_coarse_op(_ptr(L), _ptr(a), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(Q), n_tv, _ptr(Dc),
+                           None if lst is None else _ptr(lst), nl)
+    return Dc

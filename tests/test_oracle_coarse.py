@@ -1,0 +1,183 @@
+"""Pins of the oracle's block Gram-Schmidt, restriction/prolongation (Alg. 3, P = R^dag)
+and coarse operator D_c (Sec. 2).  CPU only."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_03184_amd import inputs
+from oracle_helpers import coarse_apply, coarse_dense, colour_rotate, gauge_rotate_links, rel
+
+L4 = [4, 4, 4, 4]
+A2 = [2, 2, 2, 2]
+
+
+def _agg_matrix(L, a, vecs, i, h):
+    """V^h_i with rows (local site lexicographic, spin in half, colour), columns = vectors."""
+    c = inputs.site_coords(L)
+    na = [L[m] // a[m] for m in range(4)]
+    ac = c // np.array(a)
+    aid = ac[:, 0] + na[0] * (ac[:, 1] + na[1] * (ac[:, 2] + na[2] * ac[:, 3]))
+    loc = c % np.array(a)
+    lidx = loc[:, 0] + a[0] * (loc[:, 1] + a[1] * (loc[:, 2] + a[2] * loc[:, 3]))
+    sites = np.where(aid == i)[0]
+    order = sites[np.argsort(lidx[sites])]
+    return vecs[:, order, 2 * h:2 * h + 2, :].reshape(vecs.shape[0], -1).T
+
+
+@pytest.fixture(scope="module")
+def setup_vectors():
+    U = inputs.gauge_field(L4, 0.3, 201)
+    A = oracle.clover(L4, U, 1.0, -0.1)
+    v = inputs.test_vectors(L4, 6, 202)
+    x = oracle.sap(L4, A2, U, A, v, 2, 3)  # smoothed test vectors, as in the initial phase
+    return U, A, x
+
+
+def test_T15_block_gs(setup_vectors):
+    U, A, V = setup_vectors
+    Q, T = oracle.block_gs(L4, A2, V, return_T=True)
+    n_tv = V.shape[0]
+    for i in range(16):
+        for h in range(2):
+            Vm = _agg_matrix(L4, A2, V, i, h)
+            Qm = _agg_matrix(L4, A2, Q, i, h)
+            Tm = T[i, h]
+            assert np.max(np.abs(Qm.conj().T @ Qm - np.eye(n_tv))) < 1e-13
+            assert np.max(np.abs(np.tril(Tm, -1))) == 0.0
+            d = np.diag(Tm)
+            assert np.all(d.real > 0) and np.all(d.imag == 0)
+            assert rel(Qm @ Tm, Vm) < 1e-14
+            # library Householder QR, with the phase fixed to a positive diagonal
+            q, r = np.linalg.qr(Vm)
+            ph = np.diag(r) / np.abs(np.diag(r))
+            q = q * ph[None, :]
+            kappa = np.linalg.cond(Vm)
+            assert rel(Qm, q) < 10 * kappa * 1e-15
+
+
+def test_T15_gs_gauge_covariant(setup_vectors):
+    U, A, V = setup_vectors
+    W = inputs.gauge_transform(L4, 203)
+    Q = oracle.block_gs(L4, A2, V)
+    QW = oracle.block_gs(L4, A2, colour_rotate(W, V))
+    assert rel(QW, colour_rotate(W, Q)) < 1e-13
+
+
+def test_gs_rank_deficiency_detected():
+    v = inputs.test_vectors(L4, 3, 204)
+    v[2] = 2.0 * v[0] - 0.5j * v[1]
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.block_gs(L4, A2, v)
+
+
+def test_T16_restrict_prolong(setup_vectors):
+    U, A, V = setup_vectors
+    Q = oracle.block_gs(L4, A2, V)
+    rng = np.random.default_rng(205)
+    yc = rng.standard_normal((2, 16, 2, 6)) + 1j * rng.standard_normal((2, 16, 2, 6))
+    assert rel(oracle.restrict(L4, A2, Q, oracle.prolong(L4, A2, Q, yc)), yc) < 1e-14
+    # R is the adjoint of P: <R y, yc> = <y, P yc>
+    y = inputs.test_vectors(L4, 1, 206)
+    lhs = np.vdot(oracle.restrict(L4, A2, Q, y), yc[:1])
+    rhs = np.vdot(y, oracle.prolong(L4, A2, Q, yc[:1]))
+    assert abs(lhs - rhs) / abs(rhs) < 1e-13
+    # restriction of a test vector: column k of Q^h_i restricts to T^h_i[:, k] structure,
+    # i.e. R v_k has zero entries beyond k (upper-triangular T)
+    Q2, T = oracle.block_gs(L4, A2, V, return_T=True)
+    rv = oracle.restrict(L4, A2, Q2, V)  # [n_tv][Vc][2][n_tv]
+    assert rel(np.transpose(rv, (1, 2, 3, 0)), T) < 1e-13
+
+
+def test_T17_galerkin(setup_vectors):
+    """D_c y_c = R D P y_c for random coarse vectors (matrix-free Galerkin product)."""
+    U, A, V = setup_vectors
+    Q = oracle.block_gs(L4, A2, V)
+    Dc = oracle.coarse_op(L4, A2, U, A, Q)
+    rng = np.random.default_rng(207)
+    yc = rng.standard_normal((2, 16, 2, 6)) + 1j * rng.standard_normal((2, 16, 2, 6))
+    expect = oracle.restrict(L4, A2, Q, oracle.dirac(L4, U, A, oracle.prolong(L4, A2, Q, yc)))
+    got = coarse_apply([2, 2, 2, 2], Dc, yc)
+    assert rel(got, expect) < 1e-13
+
+
+def test_T18_sigma3_symmetry(setup_vectors):
+    U, A, V = setup_vectors
+    Q = oracle.block_gs(L4, A2, V)
+    Dc = oracle.coarse_op(L4, A2, U, A, Q)
+    n_tv = V.shape[0]
+    s3 = np.diag([1.0] * n_tv + [-1.0] * n_tv)
+    M = coarse_dense([2, 2, 2, 2], Dc)
+    S = np.kron(np.eye(16), s3)
+    assert rel(S @ M, M.conj().T @ S) < 1e-13
+    # blockwise: the -mu block of i+mu is sigma3 (+mu block of i)^dag sigma3
+    from oracle_helpers import coarse_neighbour
+    for i in range(16):
+        for mu in range(4):
+            j = coarse_neighbour([2, 2, 2, 2], i, 1 + mu)
+            assert rel(Dc[j, 5 + mu], s3 @ Dc[i, 1 + mu].conj().T @ s3) < 1e-13
+    # the self block is sigma3-hermitian too
+    for i in range(16):
+        assert rel(s3 @ Dc[i, 0], Dc[i, 0].conj().T @ s3) < 1e-13
+
+
+def test_T19_gauge_invariance(setup_vectors):
+    U, A, V = setup_vectors
+    W = inputs.gauge_transform(L4, 208)
+    UW = gauge_rotate_links(L4, U, W)
+    AW = oracle.clover(L4, UW, 1.0, -0.1)
+    Dc = oracle.coarse_op(L4, A2, U, A, oracle.block_gs(L4, A2, V))
+    DcW = oracle.coarse_op(L4, A2, UW, AW, oracle.block_gs(L4, A2, colour_rotate(W, V)))
+    assert rel(DcW, Dc) < 1e-13
+
+
+def test_T20_free_field_closed_form():
+    """Free field, 6 constant test vectors e_k (+) e_k: D_c is the coarse Wilson operator,
+    self = (m0 + sum 1/a_mu), +-mu blocks = -(1/(2 a_mu)) (1 -+ g_mu) (x) 1_3."""
+    L = [4, 4, 4, 8]
+    a = [2, 2, 2, 4]
+    m0 = -0.3
+    U = inputs.unit_gauge_field(L)
+    A = oracle.clover(L, U, 1.0, m0)
+    V = inputs.volume(L)
+    vecs = np.zeros((6, V, 4, 3), np.complex128)
+    for k in range(6):
+        s, c = divmod(k, 3)
+        vecs[k, :, s, c] = 1.0
+        vecs[k, :, 2 + s, c] = 1.0
+    Q = oracle.block_gs(L, a, vecs)
+    Dc = oracle.coarse_op(L, a, U, A, Q)
+    self_expect = (m0 + sum(1.0 / x for x in a)) * np.eye(12)
+    assert np.max(np.abs(Dc[:, 0] - self_expect)) < 1e-14
+    for mu in range(4):
+        g = oracle.gamma(mu)
+        fwd = -(1.0 / (2 * a[mu])) * np.kron(np.eye(4) - g, np.eye(3))
+        bwd = -(1.0 / (2 * a[mu])) * np.kron(np.eye(4) + g, np.eye(3))
+        assert np.max(np.abs(Dc[:, 1 + mu] - fwd)) < 1e-14
+        assert np.max(np.abs(Dc[:, 5 + mu] - bwd)) < 1e-14
+
+
+@pytest.mark.parametrize("L,a", [([4, 4, 2, 4], [2, 4, 2, 2]), ([4, 2, 4, 2], [2, 2, 2, 2])])
+def test_T21_small_coarse_extents(L, a):
+    """Coarse extent 1 or 2: the per-direction blocks, summed where they coincide,
+    equal the dense R D P."""
+    U = inputs.gauge_field(L, 0.3, 211)
+    A = oracle.clover(L, U, 1.0, -0.1)
+    n_tv = 4
+    v = inputs.test_vectors(L, n_tv, 212)
+    Q = oracle.block_gs(L, a, v)
+    Dc = oracle.coarse_op(L, a, U, A, Q)
+    Lc = [L[m] // a[m] for m in range(4)]
+    Vc = int(np.prod(Lc))
+    nc = 2 * n_tv
+    units = np.eye(Vc * nc).reshape(Vc * nc, Vc, 2, n_tv)
+    RDP = oracle.restrict(L, a, Q, oracle.dirac(L, U, A, oracle.prolong(L, a, Q, units)))
+    dense = RDP.reshape(Vc * nc, Vc * nc).T
+    assert rel(coarse_dense(Lc, Dc), dense) < 1e-13
+
+
+def test_coarse_op_sampled_matches_full(setup_vectors):
+    U, A, V = setup_vectors
+    Q = oracle.block_gs(L4, A2, V)
+    full = oracle.coarse_op(L4, A2, U, A, Q)
+    part = oracle.coarse_op(L4, A2, U, A, Q, agg_list=[3, 12])
+    assert np.array_equal(part[[3, 12]], full[[3, 12]])
