@@ -1,0 +1,301 @@
+"""Benchmark of the MRHS setup path on one MI355X.
+
+One step = the initial setup phase on all test vectors at once, inputs resident in HBM:
+  sap_smooth_mrhs     SAP from x = 0 on N_tv vectors (FP32),
+  mrhs_residual_norms FP64 check ||b - D x|| / ||b|| per vector,
+  block_orthonormalize FP64 block Gram-Schmidt on the aggregates -> Q (FP32),
+  coarse_op_build     D_c (9 blocks of 2N_tv x 2N_tv complex64 per coarse site).
+Workload: 16^4 Wilson-clover lattice (synthetic links, sigma = 0.3), m0 = -0.3, csw = 1,
+N_tv = 20 complex Gaussian test vectors, 4^4 SAP blocks and aggregates, 3 SAP sweeps x
+4 MR steps.
+
+Prints one JSON line.  value = site-RHS updates per second of the whole step
+(V * N_tv * n_SAP / step time).  Also reports: the roofline of the dominant kernel
+(SAP half-sweep, FP32 ALU bound) with HIP-event timing over the timed region, the
+stencil's HBM roofline, the single-RHS FP64 GPU path for the same SAP (speedup), and the
+CPU oracle on a bounded sample (baseline only).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1601_03184_amd import inputs, mrhs  # noqa: E402
+from paper_1601_03184_amd import perfmodel as pm  # noqa: E402
+
+L = [16, 16, 16, 16]
+BLOCK = [4, 4, 4, 4]
+AGG = [4, 4, 4, 4]
+SIGMA, SEED_U, SEED_V = 0.3, 201, 202
+M0, CSW = -0.3, 1.0
+N_TV, N_SAP, N_MR = 20, 3, 4
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3      # published, with packed FP32 FMA
+FP32_ISSUE_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, no packed FP32
+WORKLOAD = ("16^4 Wilson-clover (sigma=0.3 links, m0=-0.3, csw=1), N_tv=20, SAP 4^4 blocks 3x4 FP32, "
+            "FP64 residual check, FP64 block Gram-Schmidt on 4^4 aggregates, D_c FP32")
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def sap_flops_per_call(V, n, n_sap, n_mr, block):
+    """Arithmetic the SAP call needs: block-operator MR steps on every site, the residual
+    (skipped where x is still zero: the first red half-sweep, and same-colour blocks in the
+    first black half-sweep)."""
+    Vb = int(np.prod(block))
+    inner = sum((Vb - Vb // b) for b in block) * 2 / (8.0 * Vb)   # fraction of hops inside a block
+    hop = 1320.0
+    rest = pm.STENCIL_FLOP - hop
+    mr = n_mr * (rest + hop * inner + pm.MR_EXTRA_FLOP)
+    full_res = pm.STENCIL_FLOP + pm.RESIDUAL_EXTRA_FLOP
+    first_black_res = hop * (1 - inner) + pm.RESIDUAL_EXTRA_FLOP
+    half = V / 2.0 * n
+    per_call = half * (mr) + half * (mr + first_black_res) + (n_sap - 1) * 2 * half * (mr + full_res)
+    return per_call
+
+
+def sap_bytes_per_call(V, n, n_sap, store_b, field_b):
+    """Algorithmic HBM bytes of a SAP call: per half-sweep the fields of that colour's sites
+    once, b and x of those sites (x read except in the first sweep), x written, and the
+    x halo the residual reads (2x the block volume for 4^4 blocks, 3/8 of it read-once is
+    neglected: counted once per site of the other colour)."""
+    half = V // 2
+    s = pm.SPINOR_REALS * store_b
+    f = (4 * pm.LINK_REALS + pm.CLOVER_REALS) * field_b
+    total = 0.0
+    for sweep in range(n_sap):
+        for c in range(2):
+            total += half * f
+            total += half * n * s * 2                     # b read, x written
+            if sweep > 0:
+                total += half * n * s                     # x read (own)
+            if sweep > 0 or c == 1:
+                total += half * n * s                     # halo x of the other colour
+    return total
+
+
+def make_inputs(dev):
+    U = inputs.gauge_field(L, SIGMA, SEED_U)
+    v = inputs.test_vectors(L, N_TV, SEED_V)
+    return U, v
+
+
+class Setup:
+    def __init__(self, U, v, prec, S, gs=True):
+        self.op = mrhs.Operator(L, BLOCK, AGG, torch.from_numpy(U), M0, CSW, prec=prec, short_len=S)
+        self.n = v.shape[0]
+        self.b = self.op.pack(torch.from_numpy(v))
+        self.x = self.op.empty(self.n)
+        self.ws = self.op.workspace(self.n)
+        self.res = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        if gs:
+            self.Q = self.op.empty(self.n, mrhs.DTYPE_F32)
+            self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
+            nc = 2 * self.n
+            self.Dc = torch.empty(self.op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+
+    def sap(self):
+        mrhs.sap_smooth_mrhs(self.op.handle, self.b, self.x, self.n, N_SAP, N_MR, self.ws)
+
+    def resid(self):
+        mrhs.mrhs_residual_norms(self.op.handle, self.b, self.x, self.n, self.res, self.ws)
+
+    def gs(self):
+        mrhs.block_orthonormalize(self.op.handle, self.x, self.op.dtype, self.Q, mrhs.DTYPE_F32, self.n, self.status,
+                                  self.ws)
+
+    def dc(self):
+        mrhs.coarse_op_build(self.op.handle, self.Q, mrhs.DTYPE_F32, self.n, self.Dc, self.ws)
+
+
+def time_steps(setup, steps, warmup):
+    """Returns per-step ms and per-part ms (HIP events on the stream the kernels use)."""
+    parts = ["sap", "resid", "gs", "dc"]
+    for _ in range(warmup):
+        for p in parts:
+            getattr(setup, p)()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(parts) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record()
+        for j, p in enumerate(parts):
+            getattr(setup, p)()
+            ev[s][j + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    per = {p: np.mean([ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)]) for j, p in enumerate(parts)}
+    step = np.mean([ev[s][0].elapsed_time(ev[s][-1]) for s in range(steps)])
+    return step, wall, per
+
+
+def time_call(fn, reps, warmup=2):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(U, v, x_gpu, budget_s=30.0):
+    """The oracle on the host cores: SAP on a sample of test vectors (they are independent),
+    Gram-Schmidt on all aggregates, D_c on a sample of aggregates; scaled to the full step."""
+    import oracle
+    cores = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "1000")))
+    os.environ.setdefault("OMP_NUM_THREADS", str(cores))
+    t = time.perf_counter()
+    A = oracle.clover(L, U, CSW, M0)
+    t_clover = time.perf_counter() - t
+    n_s = 2
+    t = time.perf_counter()
+    xs = oracle.sap(L, BLOCK, U, A, v[:n_s], N_SAP, N_MR)
+    t_sap = (time.perf_counter() - t) * N_TV / n_s
+    t = time.perf_counter()
+    oracle.residual_norms(L, U, A, v[:n_s], xs)
+    t_res = (time.perf_counter() - t) * N_TV / n_s
+    t = time.perf_counter()
+    Q = oracle.block_gs(L, AGG, x_gpu)
+    t_gs = time.perf_counter() - t
+    n_agg = oracle.n_aggregates(L, AGG)
+    sample = list(range(0, n_agg, n_agg // 8))[:8]
+    t = time.perf_counter()
+    oracle.coarse_op(L, AGG, U, A, Q, agg_list=sample)
+    t_dc = (time.perf_counter() - t) * n_agg / len(sample)
+    total = t_sap + t_res + t_gs + t_dc
+    V = int(np.prod(L))
+    return {
+        "value": V * N_TV * N_SAP / total,
+        "unit": "site*RHS updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": ("SAP + residual on %d of %d test vectors (scaled x%d), block GS on all %d aggregates, "
+                   "D_c on %d of %d aggregates (scaled); op set-up (%.1f s) excluded; FP64 C, OpenMP"
+                   % (n_s, N_TV, N_TV // n_s, n_agg, len(sample), n_agg, t_clover)),
+        "seconds": {"sap": t_sap, "resid": t_res, "gs": t_gs, "dc": t_dc},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-srhs", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the path would shard by domain decomposition; "
+              "no multi-GPU run is implemented)", file=sys.stderr)
+        sys.exit(2)
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_calib:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4}))
+        return
+
+    V = int(np.prod(L))
+    log("generating inputs")
+    U, v = make_inputs("cuda")
+    log("operator set-up")
+    mr = Setup(U, v, mrhs.PREC_F32, 4)
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    step_ms, wall_ms, per = time_steps(mr, args.steps, args.warmup)
+    assert int(mr.status.item()) == 0
+    res = mr.res.cpu().numpy()
+    log("step %.3f ms (wall %.3f): %s; residuals %.4f..%.4f" % (step_ms, wall_ms, per, res.min(), res.max()))
+
+    value = V * N_TV * N_SAP / (step_ms * 1e-3)
+    # dominant kernel: the SAP half-sweep (2 * N_SAP launches per call)
+    n_launch = 2 * N_SAP
+    sap_launch_ms = per["sap"] / n_launch
+    flops_launch = sap_flops_per_call(V, N_TV, N_SAP, N_MR, BLOCK) / n_launch
+    achieved = flops_launch / (sap_launch_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+            "kernel": "k_sap_half (FP32, T=%d)" % 4, "launch_ms": round(sap_launch_ms, 4),
+            "frac_of_issue_peak": round(achieved / FP32_ISSUE_PEAK_TFLOPS, 4)}
+
+    # stencil HBM roofline (the HBM-bound kernel of the path)
+    y = mr.op.empty(N_TV)
+    d_ms = time_call(lambda: mrhs.dirac_apply_mrhs(mr.op.handle, mr.b, y, N_TV), 20)
+    d_bytes = V * N_TV * pm.stencil_bytes_per_site_rhs(N_TV, 4, 4)
+    stencil = {"kernel": "k_dirac (FP32, 20 RHS)", "ms": round(d_ms, 4), "GBs": round(d_bytes / d_ms / 1e6, 1),
+               "frac_hbm": round(d_bytes / d_ms / 1e6 / HBM_PEAK_GBS, 4),
+               "site_rhs_per_s": V * N_TV / (d_ms * 1e-3)}
+    sap_bytes = sap_bytes_per_call(V, N_TV, N_SAP, 4, 4)
+    sap_info = {"ms_per_call": round(per["sap"], 4), "alg_GBs": round(sap_bytes / per["sap"] / 1e6, 1),
+                "alg_tflops": round(sap_flops_per_call(V, N_TV, N_SAP, N_MR, BLOCK) / per["sap"] / 1e9, 3)}
+
+    srhs = None
+    if not args.no_srhs:
+        log("single-RHS FP64 and MRHS FP64 paths")
+        s1 = Setup(U, v[:1], mrhs.PREC_F64, 1, gs=False)
+        srhs_ms = time_call(s1.sap, 5) * N_TV     # the same SAP, one vector per call, looped
+        m64 = Setup(U, v, mrhs.PREC_F64, 4, gs=False)
+        mrhs.mrhs_set_tiles(m64.op.handle, 2, 0)
+        m64_ms = time_call(m64.sap, 5)
+        srhs = {"srhs_fp64_sap_ms": round(srhs_ms, 3), "mrhs_fp64_sap_ms": round(m64_ms, 3),
+                "mrhs_fp32_sap_ms": round(per["sap"], 3),
+                "speedup_equal_precision": round(srhs_ms / m64_ms, 2),
+                "speedup_run_precision": round(srhs_ms / per["sap"], 2)}
+        log("srhs %s" % srhs)
+        s1.op.close()
+        m64.op.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        x_gpu = mr.op.unpack(mr.x, N_TV).cpu().numpy()
+        cpu = cpu_baseline(U, v, x_gpu)
+        log("cpu %s" % cpu)
+
+    out = {
+        "metric": "MRHS SAP setup: site*RHS updates/s and HBM GB/s vs single-RHS, same accuracy",
+        "value": value,
+        "unit": "site*RHS updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "lattice": L, "n_tv": N_TV, "sap": [N_SAP, N_MR], "block": BLOCK,
+                   "aggregate": AGG, "parallelism": "single GPU"},
+        "parts_ms": {k: round(float(x), 4) for k, x in per.items()},
+        "residual_max": float(res.max()),
+        "roofline": roof,
+        "stencil_roofline": stencil,
+        "sap": sap_info,
+        "srhs": srhs,
+        "cpu_baseline": cpu,
+    }
+    mr.op.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/*
+ * mrhs.h -- C-ABI of the MI355X (gfx950) library for the multiple-right-hand-side
+ * setup of DD-alpha-AMG (Richtmann, Heybrock, Wettig, Lattice 2015).
+ *
+ * The setup's initial phase (Sec. 2): N_tv random test vectors of dimension 12V are
+ * smoothed by the Schwarz alternating procedure (SAP) from a zero starting guess and
+ * replaced by the result; restriction R, prolongation P = R^dagger and the coarse
+ * operator D_c are then built from them.  The library runs that phase on all test
+ * vectors at once (Sec. 3, Alg. 2: the test-vector loop blocked and moved into the
+ * lowest-level kernels), in a layout with the right-hand-side index innermost
+ * (Sec. 5, the AoSoSV layout), so that the operator is read once per site for all
+ * right-hand sides (Sec. 6, mat-vec -> mat-mat).
+ *
+ * Conventions (the paper leaves them to the works it cites):
+ *   lattice extents L[0..3] for directions x,y,z,t, canonical site index
+ *   x0 + L0*(x1 + L1*(x2 + L2*x3)), periodic boundaries; spinor component
+ *   3*spin + colour; Wilson-clover operator in the DeGrand-Rossi chiral basis,
+ *     (D psi)(x) = A(x) psi(x) - 1/2 sum_mu [ (1 - g_mu) U_mu(x) psi(x+mu)
+ *                                            + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ],
+ *     A(x) = (4 + m0) + C(x), C(x) = -(csw/16) sum_{mu<nu} g_mu g_nu (Q_munu - Q_munu^dag),
+ *   Q_munu(x) the sum of the four plaquette leaves in the (mu,nu) plane at x.
+ *
+ * Memory: every pointer to field or vector data is a DEVICE pointer owned by the
+ * caller.  The library owns only what mrhs_op_create allocates (the operator's
+ * fields in kernel layout), until mrhs_op_destroy.  No call allocates device memory
+ * except mrhs_op_create; scratch space is passed in as a caller-owned workspace.
+ *
+ * Asynchrony: every call only enqueues work on the given HIP stream (a hipStream_t
+ * passed as void*, NULL = the default stream), except mrhs_op_create, mrhs_op_destroy
+ * and mrhs_pack, which synchronise that stream before returning.  Arguments are
+ * validated before anything is enqueued.
+ *
+ * Errors: every int-returning call returns 0 on success or a negative MRHS_E* code;
+ * mrhs_last_error() returns a thread-local message for the last failure.  No call
+ * throws, exits or aborts.
+ *
+ * Native vector layout (the "AoSoSV" layout of Sec. 5 with short-vector length S):
+ *   sites are re-ordered block-major: native site = blk * Vb + off, blk the SAP block
+ *   (lexicographic block coordinates), off the lexicographic local coordinate within
+ *   the block, Vb = block volume.  Right-hand side k sits in group g = k / S at lane
+ *   t = k % S.  Real component r = 2*(3*spin + colour) + (0 re | 1 im) of site (blk, off)
+ *   of rhs k is element
+ *       ((g * n_blocks + blk) * 24 + r) * Vb * S + off * S + t.
+ *   A native vector set for n_rhs right-hand sides holds ceil(n_rhs / S) groups; the
+ *   padding lanes of the last group must be zero (mrhs_pack writes them so), and stay
+ *   zero under every call (a zero right-hand side gives a zero MR step).
+ */
+#ifndef MRHS_H
+#define MRHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MRHS_OK 0
+#define MRHS_EINVAL (-1)      /* null pointer, aliasing, bad size or geometry */
+#define MRHS_EUNSUPPORTED (-2) /* a shape / precision combination this build does not handle */
+#define MRHS_EHIP (-3)        /* HIP runtime or launch error (text in mrhs_last_error) */
+#define MRHS_ERANK (-4)       /* rank-deficient aggregate in block_orthonormalize */
+#define MRHS_ERANGE (-5)      /* value outside the FP16 range in mrhs_pack */
+
+/* element types of native vectors */
+#define MRHS_DTYPE_F64 0
+#define MRHS_DTYPE_F32 1
+#define MRHS_DTYPE_F16 2
+
+/* operator precisions */
+#define MRHS_PREC_F64 0          /* FP64 fields, vectors and arithmetic */
+#define MRHS_PREC_F32 1          /* FP32 fields, vectors and arithmetic */
+#define MRHS_PREC_F32_F16STORE 2 /* FP32 fields and arithmetic, FP16 (binary16) vector storage */
+
+typedef struct mrhs_geom {
+    int32_t L[4];     /* lattice extents x,y,z,t */
+    int32_t block[4]; /* SAP block extents; must divide L; block volume <= 256 */
+    int32_t agg[4];   /* aggregate extents (Alg. 3's domains); must divide L */
+} mrhs_geom;
+
+typedef struct mrhs_op mrhs_op;
+
+/* Build the operator for one gauge field (Sec. 2's Dirac operator, readings above).
+ * links: DEVICE, complex128 interleaved (re, im), canonical [4][V][3][3] (direction,
+ *        canonical site, row, column); read during the call only.
+ * m0, csw: bare mass and clover coefficient.  prec: MRHS_PREC_*.
+ * short_len: S of the native layout, 1, 2, 4 or 8 (1 = single-RHS layout).
+ * The op keeps FP64 copies of its fields for mrhs_residual_norms in every precision.
+ * Synchronises the stream.  *out receives the handle. */
+int mrhs_op_create(const mrhs_geom *geom, const double *links, double m0, double csw, int32_t prec,
+                   int32_t short_len, void *stream, mrhs_op **out);
+int mrhs_op_destroy(mrhs_op *op);
+
+/* the operator's vector element type (MRHS_DTYPE_*) and short-vector length */
+int mrhs_op_vector_dtype(const mrhs_op *op);
+int mrhs_op_short_len(const mrhs_op *op);
+
+/* bytes of a native vector set of n_rhs right-hand sides of element type dtype */
+size_t mrhs_vector_bytes(const mrhs_op *op, int32_t n_rhs, int32_t dtype);
+/* bytes of workspace any call below needs for up to n_rhs right-hand sides (test vectors) */
+size_t mrhs_workspace_bytes(const mrhs_op *op, int32_t n_rhs);
+
+/* canonical complex128 [n_rhs][V][4][3] (DEVICE) <-> native vectors of element type dtype.
+ * mrhs_pack rounds to nearest-even and writes zero padding lanes; it synchronises the
+ * stream and returns MRHS_ERANGE if an FP16 target would overflow (|v| > 65504). */
+int mrhs_pack(const mrhs_op *op, const double *canon, void *native, int32_t dtype, int32_t n_rhs, void *stream);
+int mrhs_unpack(const mrhs_op *op, const void *native, int32_t dtype, double *canon, int32_t n_rhs, void *stream);
+
+/* y = D x on the full periodic lattice for n_rhs right-hand sides (the stencil whose
+ * operator reads are shared by all right-hand sides, Sec. 6).  x, y: native vectors of
+ * the op's element type; x != y. */
+int dirac_apply_mrhs(const mrhs_op *op, const void *x, void *y, int32_t n_rhs, void *stream);
+
+/* x = SAP(b) from a zero starting guess (Sec. 2, initial phase), n_sap sweeps over the
+ * red (even block-coordinate sum) then black SAP blocks; per colour the residual
+ * b - D x is formed on that colour's blocks, then every block j adds n_mr minimal-
+ * residual steps on D_j = I_j^T D I_j (step length 0 when <q,q> = 0).  b, x: native
+ * vectors of the op's element type, x != b; x is overwritten.  ws: workspace of at
+ * least mrhs_workspace_bytes(op, n_rhs) bytes (used when a direction holds an odd
+ * number of blocks). */
+int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* out[k] = ||b_k - D x_k||_2 / ||b_k||_2 in FP64 (FP64 fields, x and b up-converted from
+ * their storage type).  out: DEVICE double[n_rhs]. */
+int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Per aggregate i and spin half h (spins {0,1} | {2,3}), orthonormalise the n_tv columns
+ * of V^h_i (6 * aggregate volume rows: local site, spin in half, colour): V^h_i = Q^h_i T
+ * with T upper triangular, real positive diagonal (the setup of R = Q^dag, P = Q; Sec. 2,
+ * Alg. 3).  FP64 arithmetic.  V: native vectors of v_dtype; Q: native vectors of q_dtype
+ * (may alias V exactly when the types agree).  status (DEVICE int32, nullable) receives 0
+ * or 1 + (2*aggregate + h) of the first aggregate half whose Cholesky pivot falls to
+ * <= 1e-14 ||v_k||^2 (T_kk <= 1e-7 ||v_k||, the resolution limit of CholQR in FP64);
+ * such a half's Q is not meaningful.  Needs n_tv <= 32 and n_tv <= 6 * aggregate volume. */
+int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void *Q, int32_t q_dtype, int32_t n_tv,
+                         int32_t *status, void *ws, size_t ws_bytes, void *stream);
+
+/* D_c = R D P from Q (the output of block_orthonormalize, q_dtype F32 or F64), stored per
+ * coarse site i (lexicographic over L/agg) as 9 blocks [self,+x,+y,+z,+t,-x,-y,-z,-t],
+ * each 2 n_tv x 2 n_tv complex64 row-major, row = h*n_tv + k.  The self block holds the
+ * site term and the hops that stay inside the aggregate without crossing its faces; the
+ * +mu (-mu) block holds the hops across the aggregate's +mu (-mu) face.  Dc: DEVICE. */
+int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Execution tiles (right-hand sides per workgroup) of the SAP and stencil kernels; 0 keeps
+ * the current choice.  A tile must divide the op's short length and fit the block. */
+int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile);
+
+/* thread-local text of the last error */
+const char *mrhs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

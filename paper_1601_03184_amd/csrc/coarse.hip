@@ -1,0 +1,326 @@
+// coarse.hip -- the coarse operator D_c = R D P from the orthonormalised test vectors
+// (Sec. 2: the coarse-grid operator built in the setup; R = Q^dag as in Alg. 3).
+//
+// Column c = (h', k') of P is q_k' restricted to spin half h' on each aggregate.  Per
+// coarse site i the 9 stored blocks are
+//   self: Q_i^dag (A + hops that stay inside the aggregate) P_i
+//   +mu : Q_i^dag (1 - g_mu) W_mu P_{i+mu} over the sites on the +mu face   (W = -U/2)
+//   -mu : sigma3 (+mu block of i-mu)^dag sigma3
+// The last line is exact: the -mu face hop of i is the adjoint of the +mu face hop of i-mu
+// conjugated by g5, and g5 acts on the coarse index as sigma3 = diag(1, -1) over halves.
+//
+// k_coarse_cols   : per (aggregate, column c): W0[c] = (A + inside hops) P_c on every site
+//                   and Wf[mu][c] = (1 - g_mu) W_mu P_c(x + mu) on the +mu face sites
+//                   -> workspace
+// k_coarse_blocks : per (aggregate, block d in self,+x..+t) the 2N x 2N product
+//                   sum over sites and half-h components of conj(q_k) w_c, with the sites
+//                   staged through LDS in chunks
+// k_coarse_back   : the four -mu blocks by the sigma3 relation
+#include "stencil.h"
+
+namespace {
+
+constexpr int NTHR = 256;
+constexpr int CHS = 4;  // sites per LDS chunk
+
+template <typename Tq> struct CoarseArgs {
+    KGeo g;
+    int a[4], na[4], astr[4];
+    int Va, n_agg, N;
+    const int32_t *agg_sites;
+    const uint32_t *blk_coords, *loc_coords;
+    const Tq *Q;
+    float *W0;     // [2N][n_agg][Va][24]
+    float *Wf[4];  // [2N][n_agg][Va / a_mu][24]
+    float *Dc;     // [n_agg][9][2N][2N][2]
+};
+
+__device__ inline void agg_local(const int (&a)[4], int ls, int (&lc)[4])
+{
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        lc[mu] = ls % a[mu];
+        ls /= a[mu];
+    }
+}
+
+// spinor of column (h', k') of P at native site ns: q_k' masked to spin half h'
+template <typename Tc, typename Tq>
+__device__ inline void load_pcol(const KGeo &g, const Tq *Q, int hp, int kp, int ns, Spinor<Tc> &s)
+{
+    const int blk = ns / g.Vb, off = ns - blk * g.Vb;
+    const int grp = kp / g.S, t = kp - grp * g.S;
+    const size_t base = (((size_t)grp * g.nblk + blk) * 24) * g.Vb * g.S + (size_t)off * g.S + t;
+    const size_t cs = (size_t)g.Vb * g.S;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        if (c / 6 == hp) {
+            s.re[c] = (Tc)Q[base + (2 * c) * cs];
+            s.im[c] = (Tc)Q[base + (2 * c + 1) * cs];
+        } else {
+            s.re[c] = s.im[c] = Tc(0);
+        }
+    }
+}
+
+template <int MU, typename Tc, typename Tq>
+__device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int i, int ls, int ns, const int (&lc)[4],
+                                   int hp, int kp, Spinor<Tc> &w)
+{
+    if (lc[MU] + 1 < a.a[MU]) {
+        const int nn = a.agg_sites[(size_t)i * a.Va + ls + a.astr[MU]];
+        Spinor<Tc> chi;
+        load_pcol<Tc>(a.g, a.Q, hp, kp, nn, chi);
+        Tc U[18];
+        load_link(links, a.g.V, MU, ns, U);
+        hop_accumulate<MU, -1, false>(U, chi, w);
+    }
+    hop_fence(w);
+    if (lc[MU] > 0) {
+        const int nn = a.agg_sites[(size_t)i * a.Va + ls - a.astr[MU]];
+        Spinor<Tc> chi;
+        load_pcol<Tc>(a.g, a.Q, hp, kp, nn, chi);
+        Tc U[18];
+        load_link(links, a.g.V, MU, nn, U);
+        hop_accumulate<MU, +1, true>(U, chi, w);
+    }
+    hop_fence(w);
+}
+
+// local site of the f-th site on the +mu face of an aggregate (local coordinate mu = a_mu - 1)
+__device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu, int f)
+{
+    const int st = astr[mu];
+    return f % st + st * (a[mu] - 1) + st * a[mu] * (f / st);
+}
+
+template <int MU, typename Tc, typename Tq>
+__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int hp, int kp, int i, int c)
+{
+    const KGeo &g = a.g;
+    const int blk = ns / g.Vb, off = ns - blk * g.Vb;
+    int bc[4], lcb[4];
+    decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lcb);
+    const NbrSite n = nbr_fwd(g, MU, blk, off, bc, lcb);
+    Spinor<Tc> chi, w;
+    load_pcol<Tc>(g, a.Q, hp, kp, n.blk * g.Vb + n.off, chi);
+    Tc U[18];
+    load_link(links, g.V, MU, ns, U);
+    spinor_zero(w);
+    hop_accumulate<MU, -1, false>(U, chi, w);
+    // index of this site among the face sites: drop local coordinate MU
+    const int st = a.astr[MU];
+    const int f = ls % st + st * (ls / (st * a.a[MU]));
+    const int nf = a.Va / a.a[MU];
+    float *dst = a.Wf[MU] + (((size_t)c * a.n_agg + i) * nf + f) * 24;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        dst[2 * q] = (float)w.re[q];
+        dst[2 * q + 1] = (float)w.im[q];
+    }
+}
+
+// grid: (aggregate i, column c); threads: sites of the aggregate
+template <typename Tc, typename Tq>
+__global__ void __launch_bounds__(NTHR) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
+                                                      const Tc *__restrict__ clover)
+{
+    const int i = blockIdx.x, c = blockIdx.y;
+    const int hp = c / a.N, kp = c - hp * a.N;
+    for (int ls = threadIdx.x; ls < a.Va; ls += blockDim.x) {
+        const int ns = a.agg_sites[(size_t)i * a.Va + ls];
+        int lc[4];
+        agg_local(a.a, ls, lc);
+        {
+            Spinor<Tc> p, w;
+            load_pcol<Tc>(a.g, a.Q, hp, kp, ns, p);
+            clover_site(clover, a.g.V, ns, p, w);
+            hop_fence(w);
+            inside_hops<0>(a, links, i, ls, ns, lc, hp, kp, w);
+            inside_hops<1>(a, links, i, ls, ns, lc, hp, kp, w);
+            inside_hops<2>(a, links, i, ls, ns, lc, hp, kp, w);
+            inside_hops<3>(a, links, i, ls, ns, lc, hp, kp, w);
+            float *dst = a.W0 + (((size_t)c * a.n_agg + i) * a.Va + ls) * 24;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                dst[2 * q] = (float)w.re[q];
+                dst[2 * q + 1] = (float)w.im[q];
+            }
+        }
+        sched_fence();
+        if (lc[0] == a.a[0] - 1) face_column<0>(a, links, ns, ls, hp, kp, i, c);
+        sched_fence();
+        if (lc[1] == a.a[1] - 1) face_column<1>(a, links, ns, ls, hp, kp, i, c);
+        sched_fence();
+        if (lc[2] == a.a[2] - 1) face_column<2>(a, links, ns, ls, hp, kp, i, c);
+        sched_fence();
+        if (lc[3] == a.a[3] - 1) face_column<3>(a, links, ns, ls, hp, kp, i, c);
+    }
+}
+
+// grid: (aggregate i, block d = 0 self, 1..4 = +mu)
+template <typename Tq>
+__global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = a.N, N2 = 2 * N;
+    float2 *Qs = reinterpret_cast<float2 *>(smem);  // [CHS][12][N]
+    float2 *Ws = Qs + CHS * 12 * N;                // [CHS][12][2N]
+    const int i = blockIdx.x, d = blockIdx.y;
+    const int mu = d - 1;
+    const int nsites = d == 0 ? a.Va : a.Va / a.a[mu];
+    const float *Wsrc = d == 0 ? a.W0 : a.Wf[mu];
+    const int nout = N2 * N2;
+    constexpr int MAXO = 16;  // outputs per thread (2N <= 64)
+    float accr[MAXO], acci[MAXO];
+    int qo[MAXO], wo[MAXO];
+#pragma unroll
+    for (int m = 0; m < MAXO; ++m) {
+        accr[m] = acci[m] = 0.f;
+        const int e = threadIdx.x + m * NTHR;
+        const int row = e / N2, c = e - row * N2;
+        const int h = row / N, k = row - h * N;
+        qo[m] = 6 * h * N + k;   // + (sl*12 + cc) * N
+        wo[m] = 6 * h * N2 + c;  // + (sl*12 + cc) * N2
+    }
+
+    for (int s0 = 0; s0 < nsites; s0 += CHS) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < CHS * 12 * N; e += blockDim.x) {
+            const int sl = e / (12 * N), rem = e - sl * 12 * N, comp = rem / N, k = rem - comp * N;
+            const int sidx = s0 + sl;
+            float2 v = make_float2(0.f, 0.f);
+            if (sidx < nsites) {
+                const int ls = d == 0 ? sidx : face_site(a.a, a.astr, mu, sidx);
+                const int ns = a.agg_sites[(size_t)i * a.Va + ls];
+                const int blk = ns / a.g.Vb, off = ns - blk * a.g.Vb;
+                const int grp = k / a.g.S, t = k - grp * a.g.S;
+                const size_t base = (((size_t)grp * a.g.nblk + blk) * 24) * a.g.Vb * a.g.S + (size_t)off * a.g.S + t;
+                const size_t cs = (size_t)a.g.Vb * a.g.S;
+                v = make_float2((float)a.Q[base + (2 * comp) * cs], (float)a.Q[base + (2 * comp + 1) * cs]);
+            }
+            Qs[e] = v;
+        }
+        for (int e = threadIdx.x; e < CHS * 12 * N2; e += blockDim.x) {
+            const int sl = e / (12 * N2), rem = e - sl * 12 * N2, comp = rem / N2, c = rem - comp * N2;
+            const int sidx = s0 + sl;
+            float2 v = make_float2(0.f, 0.f);
+            if (sidx < nsites) {
+                const float *src = Wsrc + (((size_t)c * a.n_agg + i) * nsites + sidx) * 24;
+                v = make_float2(src[2 * comp], src[2 * comp + 1]);
+            }
+            Ws[e] = v;
+        }
+        __syncthreads();
+        // out[(h,k)][c] += sum over the chunk's sites and the 6 components of half h
+        for (int sl = 0; sl < CHS; ++sl)
+#pragma unroll 1
+            for (int cc = 0; cc < 6; ++cc) {
+                const int qb = (sl * 12 + cc) * N, wb = (sl * 12 + cc) * N2;
+#pragma unroll
+                for (int m = 0; m < MAXO; ++m) {
+                    if (threadIdx.x + m * NTHR < nout) {
+                        const float2 q = Qs[qb + qo[m]];
+                        const float2 w = Ws[wb + wo[m]];
+                        accr[m] += q.x * w.x + q.y * w.y;
+                        acci[m] += q.x * w.y - q.y * w.x;
+                    }
+                }
+            }
+    }
+    float *out = a.Dc + ((size_t)i * 9 + d) * nout * 2;
+#pragma unroll
+    for (int m = 0; m < MAXO; ++m) {
+        const int e = threadIdx.x + m * NTHR;
+        if (e < nout) {
+            out[2 * e] = accr[m];
+            out[2 * e + 1] = acci[m];
+        }
+    }
+}
+
+// D_c(i, i - mu) = sigma3 D_c(i - mu, i)^dag sigma3 ; grid (aggregate, mu)
+template <typename Tq> __global__ void k_coarse_back(CoarseArgs<Tq> a)
+{
+    const int i = blockIdx.x, mu = blockIdx.y;
+    const int N2 = 2 * a.N, nout = N2 * N2;
+    int c[4], r = i;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        c[m] = r % a.na[m];
+        r /= a.na[m];
+    }
+    c[mu] = (c[mu] - 1 + a.na[mu]) % a.na[mu];
+    const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
+    const float *src = a.Dc + ((size_t)j * 9 + 1 + mu) * nout * 2;
+    float *dst = a.Dc + ((size_t)i * 9 + 5 + mu) * nout * 2;
+    for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+        const int row = e / N2, col = e - row * N2;
+        const float s = ((row < a.N) == (col < a.N)) ? 1.f : -1.f;
+        const int t = col * N2 + row;
+        dst[2 * e] = s * src[2 * t];
+        dst[2 * e + 1] = -s * src[2 * t + 1];
+    }
+}
+
+template <typename Tc, typename Tq>
+int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc, void *ws,
+                    hipStream_t st)
+{
+    CoarseArgs<Tq> a{};
+    a.g = op->k;
+    int s = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        a.a[mu] = op->g.agg[mu];
+        a.na[mu] = op->na[mu];
+        a.astr[mu] = s;
+        s *= op->g.agg[mu];
+    }
+    a.Va = op->Va;
+    a.n_agg = op->n_agg;
+    a.N = n_tv;
+    a.agg_sites = op->agg_sites;
+    a.blk_coords = op->blk_coords;
+    a.loc_coords = op->loc_coords;
+    a.Q = Q;
+    a.Dc = (float *)Dc;
+    a.W0 = (float *)ws;
+    {
+        float *p = a.W0 + (size_t)2 * n_tv * op->n_agg * op->Va * 24;
+        for (int mu = 0; mu < 4; ++mu) {
+            a.Wf[mu] = p;
+            p += (size_t)2 * n_tv * op->n_agg * (op->Va / op->g.agg[mu]) * 24;
+        }
+    }
+    if (!a.Q || !a.Dc || !a.W0 || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
+        return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
+    hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(op->n_agg, 2 * n_tv), dim3(NTHR), 0, st, a, links, clover);
+    if (int rc = hip_check(hipGetLastError(), "k_coarse_cols launch")) return rc;
+    const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
+    hipLaunchKernelGGL((k_coarse_blocks<Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a);
+    if (int rc = hip_check(hipGetLastError(), "k_coarse_blocks launch")) return rc;
+    hipLaunchKernelGGL((k_coarse_back<Tq>), dim3(op->n_agg, 4), dim3(NTHR), 0, st, a);
+    return hip_check(hipGetLastError(), "k_coarse_back launch");
+}
+
+}  // namespace
+
+size_t ws_bytes_coarse(const mrhs_op *op, int n_tv)
+{
+    size_t sites = op->Va;
+    for (int mu = 0; mu < 4; ++mu) sites += op->Va / op->g.agg[mu];
+    return sizeof(float) * 2 * (size_t)n_tv * op->n_agg * sites * 24;
+}
+
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, hipStream_t st)
+{
+    if (2 * n_tv * 2 * n_tv > 16 * NTHR) return set_error(MRHS_EUNSUPPORTED, "more than 32 test vectors");
+    if (op->links32) {
+        if (qdt == MRHS_DTYPE_F32)
+            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, ws, st);
+        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, ws, st);
+    }
+    if (qdt == MRHS_DTYPE_F32)
+        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, ws, st);
+    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, ws, st);
+}

@@ -1,0 +1,180 @@
+// dirac.hip -- y = D x on the full lattice for many right-hand sides, and the FP64
+// residual norms ||b - D x|| / ||b||.
+//
+// One workgroup per (block, tile of T right-hand sides); thread (off, t) owns one site
+// and one right-hand side.  The T lanes of a site issue the same link and clover loads,
+// so the operator is fetched once per site for the whole tile (the mat-vec -> mat-mat
+// argument of Sec. 6); tiles of one block share an XCD's L2 through xcd_remap.
+#include "stencil.h"
+
+namespace {
+
+template <typename Ts, typename Tc, int T>
+__global__ void __launch_bounds__(256 * T) k_dirac(KGeo g, const Tc *__restrict__ links, const Tc *__restrict__ clover,
+                                                   const uint32_t *__restrict__ blk_coords,
+                                                   const uint32_t *__restrict__ loc_coords, const Ts *__restrict__ x,
+                                                   Ts *__restrict__ y, int ntiles)
+{
+    const int nwg = g.nblk * ntiles;
+    const int li = xcd_remap(blockIdx.x, nwg);
+    const int blk = li / ntiles, tile = li - blk * ntiles;
+    const int off = threadIdx.x / T, t = threadIdx.x % T;
+    if (off >= g.Vb) return;
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
+    int bc[4], lc[4];
+    decode_site(g, blk_coords, loc_coords, blk, off, bc, lc);
+    Spinor<Tc> out;
+    dirac_site_global<Tc>(g, links, clover, x, grp, tt, blk, off, bc, lc, out, NoSkip{});
+    store_spinor(g, y, grp, blk, off, tt, out);
+}
+
+// Per (block, tile): partial sums of |b - D x|^2 and |b|^2 per right-hand side, FP64.
+template <typename Ts, int T>
+__global__ void __launch_bounds__(256 * T) k_residual(KGeo g, const double *__restrict__ links,
+                                                      const double *__restrict__ clover,
+                                                      const uint32_t *__restrict__ blk_coords,
+                                                      const uint32_t *__restrict__ loc_coords, const Ts *__restrict__ b,
+                                                      const Ts *__restrict__ x, int ntiles, double *__restrict__ part)
+{
+    __shared__ double red[16][T][2];
+    const int blk = blockIdx.x % g.nblk, tile = blockIdx.x / g.nblk;
+    const int off = threadIdx.x / T, t = threadIdx.x % T;
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
+    double num = 0, den = 0;
+    if (off < g.Vb) {
+        int bc[4], lc[4];
+        decode_site(g, blk_coords, loc_coords, blk, off, bc, lc);
+        Spinor<double> Dx, bb;
+        dirac_site_global<double>(g, links, clover, x, grp, tt, blk, off, bc, lc, Dx, NoSkip{});
+        load_spinor<double>(g, b, grp, blk, off, tt, bb);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const double dr = bb.re[c] - Dx.re[c], di = bb.im[c] - Dx.im[c];
+            num += dr * dr + di * di;
+            den += bb.re[c] * bb.re[c] + bb.im[c] * bb.im[c];
+        }
+    }
+    num = wave_sum_stride(num, T);
+    den = wave_sum_stride(den, T);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < T) {
+        red[wave][lane][0] = num;
+        red[wave][lane][1] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x < T) {
+        double sn = 0, sd = 0;
+        const int nw = blockDim.x >> 6;
+        for (int w = 0; w < nw; ++w) {
+            sn += red[w][threadIdx.x][0];
+            sd += red[w][threadIdx.x][1];
+        }
+        double *p = part + (((long)tile * g.nblk + blk) * T + threadIdx.x) * 2;
+        p[0] = sn;
+        p[1] = sd;
+    }
+}
+
+// out[k] = sqrt(sum num / sum den), summed over blocks in a fixed order
+template <int T>
+__global__ void k_residual_finish(const double *__restrict__ part, int nblk, int n_rhs, double *__restrict__ out)
+{
+    __shared__ double sn[256], sd[256];
+    const int k = blockIdx.x;
+    const int tile = k / T, t = k % T;
+    double a = 0, d = 0;
+    for (int blk = threadIdx.x; blk < nblk; blk += blockDim.x) {
+        const double *p = part + (((long)tile * nblk + blk) * T + t) * 2;
+        a += p[0];
+        d += p[1];
+    }
+    sn[threadIdx.x] = a;
+    sd[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sn[threadIdx.x] += sn[threadIdx.x + s];
+            sd[threadIdx.x] += sd[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && k < n_rhs) out[k] = sqrt(sn[0]) / sqrt(sd[0]);
+}
+
+int round64(int n) { return (n + 63) / 64 * 64; }
+
+template <typename Ts, typename Tc>
+int dirac_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const void *x, void *y, int n_rhs,
+                   hipStream_t st)
+{
+    const KGeo &g = op->k;
+    const int T = op->dirac_tile;
+    const int ngrp = (n_rhs + g.S - 1) / g.S;
+    const int ntiles = ngrp * (g.S / T);
+    dim3 grid(g.nblk * ntiles), block(round64(g.Vb * T));
+    switch (T) {
+    case 1:
+        hipLaunchKernelGGL((k_dirac<Ts, Tc, 1>), grid, block, 0, st, g, links, clover, op->blk_coords, op->loc_coords,
+                           (const Ts *)x, (Ts *)y, ntiles);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_dirac<Ts, Tc, 2>), grid, block, 0, st, g, links, clover, op->blk_coords, op->loc_coords,
+                           (const Ts *)x, (Ts *)y, ntiles);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_dirac<Ts, Tc, 4>), grid, block, 0, st, g, links, clover, op->blk_coords, op->loc_coords,
+                           (const Ts *)x, (Ts *)y, ntiles);
+        break;
+    default:
+        return set_error(MRHS_EUNSUPPORTED, "dirac tile not built");
+    }
+    return hip_check(hipGetLastError(), "k_dirac launch");
+}
+
+template <typename Ts>
+int residual_dispatch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
+{
+    const KGeo &g = op->k;
+    constexpr int T = 1;
+    const int ngrp = (n_rhs + g.S - 1) / g.S;
+    const int ntiles = ngrp * g.S;
+    double *part = (double *)ws;
+    hipLaunchKernelGGL((k_residual<Ts, T>), dim3(g.nblk * ntiles), dim3(round64(g.Vb * T)), 0, st, g, op->links64,
+                       op->clover64, op->blk_coords, op->loc_coords, (const Ts *)b, (const Ts *)x, ntiles, part);
+    if (int rc = hip_check(hipGetLastError(), "k_residual launch")) return rc;
+    hipLaunchKernelGGL((k_residual_finish<T>), dim3(n_rhs), dim3(256), 0, st, part, g.nblk, n_rhs, out);
+    return hip_check(hipGetLastError(), "k_residual_finish launch");
+}
+
+}  // namespace
+
+int launch_dirac(const mrhs_op *op, const void *x, void *y, int n_rhs, hipStream_t st)
+{
+    switch (op->prec) {
+    case MRHS_PREC_F64:
+        return dirac_dispatch<double, double>(op, op->links64, op->clover64, x, y, n_rhs, st);
+    case MRHS_PREC_F32:
+        return dirac_dispatch<float, float>(op, op->links32, op->clover32, x, y, n_rhs, st);
+    default:
+        return dirac_dispatch<__half, float>(op, op->links32, op->clover32, x, y, n_rhs, st);
+    }
+}
+
+size_t ws_bytes_residual(const mrhs_op *op, int n_rhs)
+{
+    const KGeo &g = op->k;
+    const int ngrp = (n_rhs + g.S - 1) / g.S;
+    return (size_t)ngrp * g.S * g.nblk * 2 * sizeof(double);
+}
+
+int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
+{
+    switch (op->dtype) {
+    case MRHS_DTYPE_F64:
+        return residual_dispatch<double>(op, b, x, n_rhs, out, ws, st);
+    case MRHS_DTYPE_F32:
+        return residual_dispatch<float>(op, b, x, n_rhs, out, ws, st);
+    default:
+        return residual_dispatch<__half>(op, b, x, n_rhs, out, ws, st);
+    }
+}

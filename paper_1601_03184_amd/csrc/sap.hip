@@ -1,0 +1,307 @@
+// sap.hip -- the Schwarz alternating procedure on all right-hand sides at once.
+//
+// One launch per colour half-sweep.  Workgroup = one SAP block of that colour x a tile
+// of T right-hand sides; thread (off, t) owns one site of the block and one right-hand
+// side.  The workgroup
+//   1. forms the residual r = b - D x on its block (full stencil, neighbours from global
+//      memory; skipped where x is known to be zero),
+//   2. runs n_mr minimal-residual steps on the block operator D_j = I_j^T D I_j with the
+//      block residual rho kept in LDS ([24][Vb][T], conflict-free for the thread order),
+//      the two inner products per step reduced across the block with wavefront shuffles
+//      and one LDS exchange, and the correction e kept in registers,
+//   3. writes x|_j (+)= e.
+// The links and clover of a site are loaded once per stencil for all T lanes of the site.
+#include "stencil.h"
+
+namespace {
+
+template <typename Ts, typename Tc> struct SapArgs {
+    KGeo g;
+    const Tc *links, *clover;
+    const uint32_t *blk_coords, *loc_coords;
+    const int32_t *blocks;  // block ids of this colour
+    int nblocks;            // number of blocks of this colour
+    int ntiles;             // right-hand-side tiles per block
+    int colour;
+    int mode;               // 0: x = 0 everywhere; 1: x = 0 on this colour's blocks; 2: general
+    int n_mr;
+    const Ts *b;
+    const Ts *xr;           // where neighbours' x is read (x itself, or a snapshot)
+    Ts *x;
+};
+
+// q = D_j rho at site off for lane t, rho read from LDS; hops leaving the block dropped.
+template <int MU, typename Tc>
+__device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, const Tc *rho_s, int T, int blk, int off,
+                                  int t, const int (&lc)[4], Spinor<Tc> &q)
+{
+    const long ns = (long)blk * g.Vb + off;
+    const int str = g.Vb * T;
+    int noff = -1;
+    if (lc[MU] + 1 < g.b[MU]) noff = off + g.ostr[MU];
+    else if (g.nb[MU] == 1) noff = off - (g.b[MU] - 1) * g.ostr[MU];
+    if (noff >= 0) {
+        Spinor<Tc> chi;
+        const Tc *p = rho_s + noff * T + t;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            chi.re[c] = p[(2 * c) * str];
+            chi.im[c] = p[(2 * c + 1) * str];
+        }
+        Tc U[18];
+        load_link(links, g.V, MU, ns, U);
+        hop_accumulate<MU, -1, false>(U, chi, q);
+    }
+    hop_fence(q);
+    noff = -1;
+    if (lc[MU] > 0) noff = off - g.ostr[MU];
+    else if (g.nb[MU] == 1) noff = off + (g.b[MU] - 1) * g.ostr[MU];
+    if (noff >= 0) {
+        Spinor<Tc> chi;
+        const Tc *p = rho_s + noff * T + t;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            chi.re[c] = p[(2 * c) * str];
+            chi.im[c] = p[(2 * c + 1) * str];
+        }
+        Tc U[18];
+        load_link(links, g.V, MU, (long)blk * g.Vb + noff, U);
+        hop_accumulate<MU, +1, true>(U, chi, q);
+    }
+}
+
+template <typename Ts, typename Tc, int T>
+__global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const KGeo &g = a.g;
+    Tc *rho_s = reinterpret_cast<Tc *>(smem);
+    const int str = g.Vb * T;
+    Tc *red_s = rho_s + 24 * str;  // [waves][T][3]
+
+    const int nwg = a.nblocks * a.ntiles;
+    const int li = xcd_remap(blockIdx.x, nwg);
+    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
+    const int blk = a.blocks[bi];
+    const int off = threadIdx.x / T, t = threadIdx.x % T;
+    const bool active = off < g.Vb;
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
+    int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
+    if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
+
+    // 1. residual on the block
+    if (active) {
+        Spinor<Tc> r;
+        if (a.mode != 0) {
+            const int colour = a.colour, mode = a.mode;
+            const uint32_t *bcs = a.blk_coords;
+            auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
+            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+            Spinor<Tc> bb;
+            load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                r.re[c] = bb.re[c] - r.re[c];
+                r.im[c] = bb.im[c] - r.im[c];
+            }
+        } else {
+            load_spinor<Tc>(g, a.b, grp, blk, off, tt, r);
+        }
+        Tc *p = rho_s + off * T + t;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            p[(2 * c) * str] = r.re[c];
+            p[(2 * c + 1) * str] = r.im[c];
+        }
+    }
+
+    // 2. minimal residual on the block operator
+    Spinor<Tc> e;
+    spinor_zero(e);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int it = 0; it < a.n_mr; ++it) {
+        __syncthreads();
+        Spinor<Tc> q;
+        Tc qq = 0, qrr = 0, qri = 0;
+        // reload the block's fields from cache in every step rather than keeping
+        // 216 of them in registers across the loop
+        const Tc *links = opaque_ptr(a.links), *clover = opaque_ptr(a.clover);
+        if (active) {
+            const Tc *p = rho_s + off * T + t;
+            {
+                Spinor<Tc> own;
+#pragma unroll
+                for (int c = 0; c < 12; ++c) {
+                    own.re[c] = p[(2 * c) * str];
+                    own.im[c] = p[(2 * c + 1) * str];
+                }
+                clover_site(clover, g.V, (long)blk * g.Vb + off, own, q);
+            }
+            hop_fence(q);
+            block_hops<0>(g, links, rho_s, T, blk, off, t, lc, q);
+            hop_fence(q);
+            block_hops<1>(g, links, rho_s, T, blk, off, t, lc, q);
+            hop_fence(q);
+            block_hops<2>(g, links, rho_s, T, blk, off, t, lc, q);
+            hop_fence(q);
+            block_hops<3>(g, links, rho_s, T, blk, off, t, lc, q);
+            hop_fence(q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const Tc orr = p[(2 * c) * str], ori = p[(2 * c + 1) * str];
+                qq += q.re[c] * q.re[c] + q.im[c] * q.im[c];
+                qrr += q.re[c] * orr + q.im[c] * ori;
+                qri += q.re[c] * ori - q.im[c] * orr;
+            }
+        } else {
+            spinor_zero(q);
+        }
+        qq = wave_sum_stride(qq, T);
+        qrr = wave_sum_stride(qrr, T);
+        qri = wave_sum_stride(qri, T);
+        if (lane < T) {
+            red_s[(wave * T + lane) * 3 + 0] = qq;
+            red_s[(wave * T + lane) * 3 + 1] = qrr;
+            red_s[(wave * T + lane) * 3 + 2] = qri;
+        }
+        __syncthreads();
+        Tc sqq = 0, sr = 0, si = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            sqq += red_s[(w * T + t) * 3 + 0];
+            sr += red_s[(w * T + t) * 3 + 1];
+            si += red_s[(w * T + t) * 3 + 2];
+        }
+        const Tc ar = sqq > Tc(0) ? sr / sqq : Tc(0);
+        const Tc ai = sqq > Tc(0) ? si / sqq : Tc(0);
+        if (active) {
+            Tc *p = rho_s + off * T + t;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const Tc rr = p[(2 * c) * str], ri = p[(2 * c + 1) * str];
+                e.re[c] += ar * rr - ai * ri;
+                e.im[c] += ar * ri + ai * rr;
+                p[(2 * c) * str] = rr - (ar * q.re[c] - ai * q.im[c]);
+                p[(2 * c + 1) * str] = ri - (ar * q.im[c] + ai * q.re[c]);
+            }
+        }
+    }
+
+    // 3. x|_j (+)= e
+    if (active) {
+        if (a.mode == 2) {
+            Spinor<Tc> xo;
+            load_spinor<Tc>(g, a.x, grp, blk, off, tt, xo);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                e.re[c] += xo.re[c];
+                e.im[c] += xo.im[c];
+            }
+        }
+        store_spinor(g, a.x, grp, blk, off, tt, e);
+    }
+}
+
+template <typename Ts> __global__ void k_fill_zero(Ts *__restrict__ p, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = Ts(0);
+}
+
+template <typename Ts> __global__ void k_copy(const Ts *__restrict__ s, Ts *__restrict__ d, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+int round64(int n) { return (n + 63) / 64 * 64; }
+
+template <typename Ts, typename Tc, int T> int set_lds(size_t bytes)
+{
+    static size_t done = 0;
+    if (bytes > 65536 && bytes > done) {
+        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_sap_half<Ts, Tc, T>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+                               "hipFuncSetAttribute(sap LDS)"))
+            return rc;
+        done = bytes;
+    }
+    return MRHS_OK;
+}
+
+template <typename Ts, typename Tc, int T> int launch_half(const SapArgs<Ts, Tc> &a, size_t max_lds, hipStream_t st)
+{
+    const KGeo &g = a.g;
+    const int threads = round64(g.Vb * T);
+    const size_t lds = sizeof(Tc) * (24 * (size_t)g.Vb * T + (size_t)(threads / 64) * T * 3);
+    if (lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "SAP tile exceeds the LDS of a workgroup");
+    if (int rc = set_lds<Ts, Tc, T>(lds)) return rc;
+    hipLaunchKernelGGL((k_sap_half<Ts, Tc, T>), dim3(a.nblocks * a.ntiles), dim3(threads), lds, st, a);
+    return hip_check(hipGetLastError(), "k_sap_half launch");
+}
+
+template <typename Ts, typename Tc>
+int sap_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const void *b, void *x, int n_rhs, int n_sap,
+                 int n_mr, void *ws, hipStream_t st)
+{
+    const KGeo &g = op->k;
+    const int T = op->sap_tile;
+    const int ngrp = (n_rhs + g.S - 1) / g.S;
+    const long nel = (long)native_elems(op, n_rhs);
+    if (n_sap == 0) {
+        hipLaunchKernelGGL(k_fill_zero<Ts>, dim3(1024), dim3(256), 0, st, (Ts *)x, nel);
+        return hip_check(hipGetLastError(), "k_fill_zero launch");
+    }
+    SapArgs<Ts, Tc> a{};
+    a.g = g;
+    a.links = links;
+    a.clover = clover;
+    a.blk_coords = op->blk_coords;
+    a.loc_coords = op->loc_coords;
+    a.ntiles = ngrp * (g.S / T);
+    a.n_mr = n_mr;
+    a.b = (const Ts *)b;
+    a.x = (Ts *)x;
+    Ts *snap = (Ts *)ws;
+    for (int s = 0; s < n_sap; ++s)
+        for (int c = 0; c < 2; ++c) {
+            if (op->n_colour[c] == 0) continue;
+            a.colour = c;
+            a.blocks = op->colour_blocks + (c == 0 ? 0 : op->n_colour[0]);
+            a.nblocks = op->n_colour[c];
+            a.mode = s == 0 ? c : 2;
+            a.xr = a.x;
+            if (a.mode == 2 && op->odd_blocks) {
+                // same-coloured blocks touch across the periodic wrap: read neighbours
+                // from a snapshot taken before this colour's updates
+                hipLaunchKernelGGL(k_copy<Ts>, dim3(2048), dim3(256), 0, st, (const Ts *)x, snap, nel);
+                if (int rc = hip_check(hipGetLastError(), "k_copy launch")) return rc;
+                a.xr = snap;
+            }
+            int rc;
+            switch (T) {
+            case 1: rc = launch_half<Ts, Tc, 1>(a, op->max_lds, st); break;
+            case 2: rc = launch_half<Ts, Tc, 2>(a, op->max_lds, st); break;
+            case 4: rc = launch_half<Ts, Tc, 4>(a, op->max_lds, st); break;
+            default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
+            }
+            if (rc) return rc;
+        }
+    return MRHS_OK;
+}
+
+}  // namespace
+
+size_t ws_bytes_sap(const mrhs_op *op, int n_rhs)
+{
+    return op->odd_blocks ? native_elems(op, n_rhs) * dtype_size(op->dtype) : 0;
+}
+
+int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st)
+{
+    switch (op->prec) {
+    case MRHS_PREC_F64:
+        return sap_dispatch<double, double>(op, op->links64, op->clover64, b, x, n_rhs, n_sap, n_mr, ws, st);
+    case MRHS_PREC_F32:
+        return sap_dispatch<float, float>(op, op->links32, op->clover32, b, x, n_rhs, n_sap, n_mr, ws, st);
+    default:
+        return sap_dispatch<__half, float>(op, op->links32, op->clover32, b, x, n_rhs, n_sap, n_mr, ws, st);
+    }
+}

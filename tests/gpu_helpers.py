@@ -1,0 +1,48 @@
+"""Shared set-up for the GPU parity tests: operators built through the C-ABI binding,
+inputs from the seeded generators, expected values from the oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1601_03184_amd import inputs
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def announce(msg):
+    """Name the case before a GPU step (flushed, so it survives a crash)."""
+    print("[gpu-case] " + msg, file=sys.stderr, flush=True)
+
+
+def per_rhs_rel(got, ref):
+    """max over right-hand sides of ||got_k - ref_k|| / ||ref_k||"""
+    n = ref.shape[0]
+    g = got.reshape(n, -1)
+    r = ref.reshape(n, -1)
+    return float(np.max(np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)))
+
+
+class Case:
+    """A gauge field with its oracle site term, cached per (L, sigma, seed, m0, csw)."""
+    _cache = {}
+
+    def __init__(self, L, sigma, seed, m0, csw=1.0):
+        key = (tuple(L), sigma, seed, m0, csw)
+        if key not in Case._cache:
+            U = inputs.gauge_field(L, sigma, seed)
+            A = oracle.clover(L, U, csw, m0)
+            Case._cache[key] = (U, A)
+        self.U, self.A = Case._cache[key]
+        self.L, self.m0, self.csw = list(L), m0, csw
+
+    def op(self, block, agg=None, prec=1, short_len=4):
+        from paper_1601_03184_amd import mrhs
+        agg = block if agg is None else agg
+        return mrhs.Operator(self.L, block, agg, torch.from_numpy(self.U), self.m0, self.csw, prec=prec,
+                             short_len=short_len)
