@@ -27,7 +27,7 @@ import torch
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_1601_03184_amd import inputs, mrhs  # noqa: E402
+from paper_1601_03184_amd import autotune, inputs, mrhs  # noqa: E402
 from paper_1601_03184_amd import perfmodel as pm  # noqa: E402
 
 L = [16, 16, 16, 16]
@@ -219,6 +219,8 @@ def main():
     U, v = make_inputs("cuda")
     log("operator set-up")
     mr = Setup(U, v, mrhs.PREC_F32, 4)
+    tiles = autotune.autotune(mr.op, N_TV, N_SAP, N_MR)
+    log("autotuned tiles: %s" % tiles)
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
     step_ms, wall_ms, per = time_steps(mr, args.steps, args.warmup)
     assert int(mr.status.item()) == 0
@@ -233,14 +235,14 @@ def main():
     achieved = flops_launch / (sap_launch_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel": "k_sap_half (FP32, T=%d)" % 4, "launch_ms": round(sap_launch_ms, 4),
+            "kernel": "k_sap_half (FP32, tile %d)" % tiles["sap"], "launch_ms": round(sap_launch_ms, 4),
             "frac_of_issue_peak": round(achieved / FP32_ISSUE_PEAK_TFLOPS, 4)}
 
     # stencil HBM roofline (the HBM-bound kernel of the path)
     y = mr.op.empty(N_TV)
     d_ms = time_call(lambda: mrhs.dirac_apply_mrhs(mr.op.handle, mr.b, y, N_TV), 20)
     d_bytes = V * N_TV * pm.stencil_bytes_per_site_rhs(N_TV, 4, 4)
-    stencil = {"kernel": "k_dirac (FP32, 20 RHS)", "ms": round(d_ms, 4), "GBs": round(d_bytes / d_ms / 1e6, 1),
+    stencil = {"kernel": "k_dirac (FP32, 20 RHS, tile %d)" % tiles["dirac"], "ms": round(d_ms, 4), "GBs": round(d_bytes / d_ms / 1e6, 1),
                "frac_hbm": round(d_bytes / d_ms / 1e6 / HBM_PEAK_GBS, 4),
                "site_rhs_per_s": V * N_TV / (d_ms * 1e-3)}
     sap_bytes = sap_bytes_per_call(V, N_TV, N_SAP, 4, 4)
@@ -284,7 +286,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "lattice": L, "n_tv": N_TV, "sap": [N_SAP, N_MR], "block": BLOCK,
-                   "aggregate": AGG, "parallelism": "single GPU"},
+                   "aggregate": AGG, "parallelism": "single GPU",
+                   "tiles": {"sap": tiles["sap"], "dirac": tiles["dirac"]}},
         "parts_ms": {k: round(float(x), 4) for k, x in per.items()},
         "residual_max": float(res.max()),
         "roofline": roof,

@@ -225,7 +225,7 @@ int mrhs_op_create(const mrhs_geom *geom, const double *links, double m0, double
     if (!rc) rc = hip_check(hipMemcpyAsync(op->agg_sites, asites.data(), sizeof(int32_t) * asites.size(), hipMemcpyHostToDevice, st), "copy");
     if (!rc) rc = launch_build_fields(op, links, m0, csw, st);
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize(op_create)");
-    op->sap_tile = pick_tile(op, prec == MRHS_PREC_F64 ? 1 : 4, true);
+    op->sap_tile = pick_tile(op, prec == MRHS_PREC_F64 ? 1 : 2, true);
     op->dirac_tile = pick_tile(op, prec == MRHS_PREC_F64 ? 1 : 4, false);
     if (rc) {
         free_op(op);

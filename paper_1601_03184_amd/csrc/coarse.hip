@@ -16,12 +16,15 @@
 //                   sum over sites and half-h components of conj(q_k) w_c, with the sites
 //                   staged through LDS in chunks
 // k_coarse_back   : the four -mu blocks by the sigma3 relation
+#include <algorithm>
+
 #include "stencil.h"
 
 namespace {
 
 constexpr int NTHR = 256;
-constexpr int CHS = 4;  // sites per LDS chunk
+constexpr int NW = NTHR / 64;
+constexpr int CHS = 8;  // sites per LDS chunk
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
@@ -30,8 +33,9 @@ template <typename Tq> struct CoarseArgs {
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
-    float *W0;     // [2N][n_agg][Va][24]
-    float *Wf[4];  // [2N][n_agg][Va / a_mu][24]
+    int ngrp;      // groups of S test vectors
+    float *W0;     // [2][ngrp][n_agg][24][Va][S]
+    float *Wf[4];  // [2][ngrp][n_agg][24][Va / a_mu][S]
     float *Dc;     // [n_agg][9][2N][2N][2]
 };
 
@@ -87,6 +91,14 @@ __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int
     hop_fence(w);
 }
 
+// workspace element of column (h', k' = grp*S + t), aggregate i, real component r, site sidx
+// of a set of nsites sites per aggregate
+template <typename Tq>
+__device__ inline size_t wcol_index(const CoarseArgs<Tq> &a, int hp, int grp, int i, int r, int nsites, int sidx, int t)
+{
+    return (((((size_t)hp * a.ngrp + grp) * a.n_agg + i) * 24 + r) * nsites + sidx) * a.g.S + t;
+}
+
 // local site of the f-th site on the +mu face of an aggregate (local coordinate mu = a_mu - 1)
 __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu, int f)
 {
@@ -95,7 +107,8 @@ __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu,
 }
 
 template <int MU, typename Tc, typename Tq>
-__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int hp, int kp, int i, int c)
+__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int hp, int kp, int i,
+                                   int grp, int t)
 {
     const KGeo &g = a.g;
     const int blk = ns / g.Vb, off = ns - blk * g.Vb;
@@ -112,22 +125,28 @@ __device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int
     const int st = a.astr[MU];
     const int f = ls % st + st * (ls / (st * a.a[MU]));
     const int nf = a.Va / a.a[MU];
-    float *dst = a.Wf[MU] + (((size_t)c * a.n_agg + i) * nf + f) * 24;
+    float *dst = a.Wf[MU];
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
-        dst[2 * q] = (float)w.re[q];
-        dst[2 * q + 1] = (float)w.im[q];
+        dst[wcol_index(a, hp, grp, i, 2 * q, nf, f, t)] = (float)w.re[q];
+        dst[wcol_index(a, hp, grp, i, 2 * q + 1, nf, f, t)] = (float)w.im[q];
     }
 }
 
-// grid: (aggregate i, column c); threads: sites of the aggregate
+// grid: (aggregate i, h' * ngrp + group); threads: (site ls, lane t), test vector k' = group*S + t.
+// The S lanes of a site read the S test vectors of a group from one contiguous run.
+template <typename Tc> constexpr int cols_threads() { return sizeof(Tc) == 8 ? 512 : 1024; }
+
 template <typename Tc, typename Tq>
-__global__ void __launch_bounds__(NTHR) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
+__global__ void __launch_bounds__(cols_threads<Tc>()) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
                                                       const Tc *__restrict__ clover)
 {
-    const int i = blockIdx.x, c = blockIdx.y;
-    const int hp = c / a.N, kp = c - hp * a.N;
-    for (int ls = threadIdx.x; ls < a.Va; ls += blockDim.x) {
+    const int i = blockIdx.x;
+    const int hp = blockIdx.y / a.ngrp, grp = blockIdx.y - hp * a.ngrp;
+    const int S = a.g.S;
+    for (int e = threadIdx.x; e < a.Va * S; e += blockDim.x) {
+        const int ls = e / S, t = e - ls * S;
+        const int kp = grp * S + t;
         const int ns = a.agg_sites[(size_t)i * a.Va + ls];
         int lc[4];
         agg_local(a.a, ls, lc);
@@ -140,25 +159,34 @@ __global__ void __launch_bounds__(NTHR) k_coarse_cols(CoarseArgs<Tq> a, const Tc
             inside_hops<1>(a, links, i, ls, ns, lc, hp, kp, w);
             inside_hops<2>(a, links, i, ls, ns, lc, hp, kp, w);
             inside_hops<3>(a, links, i, ls, ns, lc, hp, kp, w);
-            float *dst = a.W0 + (((size_t)c * a.n_agg + i) * a.Va + ls) * 24;
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                dst[2 * q] = (float)w.re[q];
-                dst[2 * q + 1] = (float)w.im[q];
+                a.W0[wcol_index(a, hp, grp, i, 2 * q, a.Va, ls, t)] = (float)w.re[q];
+                a.W0[wcol_index(a, hp, grp, i, 2 * q + 1, a.Va, ls, t)] = (float)w.im[q];
             }
         }
         sched_fence();
-        if (lc[0] == a.a[0] - 1) face_column<0>(a, links, ns, ls, hp, kp, i, c);
+        if (lc[0] == a.a[0] - 1) face_column<0>(a, links, ns, ls, hp, kp, i, grp, t);
         sched_fence();
-        if (lc[1] == a.a[1] - 1) face_column<1>(a, links, ns, ls, hp, kp, i, c);
+        if (lc[1] == a.a[1] - 1) face_column<1>(a, links, ns, ls, hp, kp, i, grp, t);
         sched_fence();
-        if (lc[2] == a.a[2] - 1) face_column<2>(a, links, ns, ls, hp, kp, i, c);
+        if (lc[2] == a.a[2] - 1) face_column<2>(a, links, ns, ls, hp, kp, i, grp, t);
         sched_fence();
-        if (lc[3] == a.a[3] - 1) face_column<3>(a, links, ns, ls, hp, kp, i, c);
+        if (lc[3] == a.a[3] - 1) face_column<3>(a, links, ns, ls, hp, kp, i, grp, t);
     }
 }
 
-// grid: (aggregate i, block d = 0 self, 1..4 = +mu)
+// grid: (aggregate i, block d = 0 self, 1..4 = +mu).  The 2N x 2N block is a sum over the
+// block's sites and the 6 components of each spin half: rows (h, k) = conj(q_k) of half h,
+// columns c = the workspace columns.  Sites are staged through LDS in chunks of CHS; the
+// products run on v_mfma_f32_16x16x4f32: the block is cut into 16x16 tiles (per half:
+// ceil(N/16) x ceil(2N/16)), the wavefronts take tiles round-robin, a K step is 4 of the
+// (site, component) rows, and complex = 4 real products.  Lane l supplies
+// A[l%16][l/16] = conj(q)[row][kk] and B[l/16][l%16] = w[kk][col], holds D[4(l/16)+r][l%16].
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
+
 template <typename Tq>
 __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
 {
@@ -170,19 +198,12 @@ __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
     const int mu = d - 1;
     const int nsites = d == 0 ? a.Va : a.Va / a.a[mu];
     const float *Wsrc = d == 0 ? a.W0 : a.Wf[mu];
-    const int nout = N2 * N2;
-    constexpr int MAXO = 16;  // outputs per thread (2N <= 64)
-    float accr[MAXO], acci[MAXO];
-    int qo[MAXO], wo[MAXO];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int TR = (N + 15) / 16, TC = (N2 + 15) / 16, ntile = 2 * TR * TC;
+    constexpr int MAXT = 4;  // tiles per wavefront (N <= 32: at most 16 tiles, 4 wavefronts)
+    f4 accr[MAXT], acci[MAXT];
 #pragma unroll
-    for (int m = 0; m < MAXO; ++m) {
-        accr[m] = acci[m] = 0.f;
-        const int e = threadIdx.x + m * NTHR;
-        const int row = e / N2, c = e - row * N2;
-        const int h = row / N, k = row - h * N;
-        qo[m] = 6 * h * N + k;   // + (sl*12 + cc) * N
-        wo[m] = 6 * h * N2 + c;  // + (sl*12 + cc) * N2
-    }
+    for (int m = 0; m < MAXT; ++m) accr[m] = acci[m] = f4{0.f, 0.f, 0.f, 0.f};
 
     for (int s0 = 0; s0 < nsites; s0 += CHS) {
         __syncthreads();
@@ -206,35 +227,48 @@ __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
             const int sidx = s0 + sl;
             float2 v = make_float2(0.f, 0.f);
             if (sidx < nsites) {
-                const float *src = Wsrc + (((size_t)c * a.n_agg + i) * nsites + sidx) * 24;
-                v = make_float2(src[2 * comp], src[2 * comp + 1]);
+                const int hp = c / N, kp = c - hp * N;
+                const int grp = kp / a.g.S, t = kp - grp * a.g.S;
+                v = make_float2(Wsrc[wcol_index(a, hp, grp, i, 2 * comp, nsites, sidx, t)],
+                                Wsrc[wcol_index(a, hp, grp, i, 2 * comp + 1, nsites, sidx, t)]);
             }
             Ws[e] = v;
         }
         __syncthreads();
-        // out[(h,k)][c] += sum over the chunk's sites and the 6 components of half h
-        for (int sl = 0; sl < CHS; ++sl)
-#pragma unroll 1
-            for (int cc = 0; cc < 6; ++cc) {
-                const int qb = (sl * 12 + cc) * N, wb = (sl * 12 + cc) * N2;
 #pragma unroll
-                for (int m = 0; m < MAXO; ++m) {
-                    if (threadIdx.x + m * NTHR < nout) {
-                        const float2 q = Qs[qb + qo[m]];
-                        const float2 w = Ws[wb + wo[m]];
-                        accr[m] += q.x * w.x + q.y * w.y;
-                        acci[m] += q.x * w.y - q.y * w.x;
-                    }
-                }
+        for (int m = 0; m < MAXT; ++m) {
+            const int tile = wave + NW * m;
+            if (tile >= ntile) break;
+            const int h = tile / (TR * TC), rem = tile - h * TR * TC, tr = rem / TC, tc = rem - tr * TC;
+            const int k = tr * 16 + (lane & 15);   // output row within the half (A row)
+            const int c = tc * 16 + (lane & 15);   // output column (B column)
+            for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
+                const int kk = kk0 + (lane >> 4), sl = kk / 6, comp = 6 * h + kk % 6;
+                const float2 q = k < N ? Qs[(sl * 12 + comp) * N + k] : make_float2(0.f, 0.f);
+                const float2 w = c < N2 ? Ws[(sl * 12 + comp) * N2 + c] : make_float2(0.f, 0.f);
+                // conj(q) w
+                accr[m] = mfma32(q.x, w.x, accr[m]);
+                accr[m] = mfma32(q.y, w.y, accr[m]);
+                acci[m] = mfma32(q.x, w.y, acci[m]);
+                acci[m] = mfma32(-q.y, w.x, acci[m]);
             }
+        }
     }
-    float *out = a.Dc + ((size_t)i * 9 + d) * nout * 2;
+    float *out = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
 #pragma unroll
-    for (int m = 0; m < MAXO; ++m) {
-        const int e = threadIdx.x + m * NTHR;
-        if (e < nout) {
-            out[2 * e] = accr[m];
-            out[2 * e + 1] = acci[m];
+    for (int m = 0; m < MAXT; ++m) {
+        const int tile = wave + NW * m;
+        if (tile >= ntile) break;
+        const int h = tile / (TR * TC), rem = tile - h * TR * TC, tr = rem / TC, tc = rem - tr * TC;
+        const int c = tc * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = tr * 16 + 4 * (lane >> 4) + r;
+            if (k < N && c < N2) {
+                const size_t e = (size_t)(h * N + k) * N2 + c;
+                out[2 * e] = accr[m][r];
+                out[2 * e + 1] = acci[m][r];
+            }
         }
     }
 }
@@ -279,6 +313,7 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.Va = op->Va;
     a.n_agg = op->n_agg;
     a.N = n_tv;
+    a.ngrp = (n_tv + op->k.S - 1) / op->k.S;
     a.agg_sites = op->agg_sites;
     a.blk_coords = op->blk_coords;
     a.loc_coords = op->loc_coords;
@@ -286,15 +321,17 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.Dc = (float *)Dc;
     a.W0 = (float *)ws;
     {
-        float *p = a.W0 + (size_t)2 * n_tv * op->n_agg * op->Va * 24;
+        const size_t cols = (size_t)2 * a.ngrp * op->k.S;  // padded columns
+        float *p = a.W0 + cols * op->n_agg * op->Va * 24;
         for (int mu = 0; mu < 4; ++mu) {
             a.Wf[mu] = p;
-            p += (size_t)2 * n_tv * op->n_agg * (op->Va / op->g.agg[mu]) * 24;
+            p += cols * op->n_agg * (op->Va / op->g.agg[mu]) * 24;
         }
     }
     if (!a.Q || !a.Dc || !a.W0 || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
-    hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(op->n_agg, 2 * n_tv), dim3(NTHR), 0, st, a, links, clover);
+    const int cthreads = std::min(cols_threads<Tc>(), (op->Va * op->k.S + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(op->n_agg, 2 * a.ngrp), dim3(cthreads), 0, st, a, links, clover);
     if (int rc = hip_check(hipGetLastError(), "k_coarse_cols launch")) return rc;
     const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
     hipLaunchKernelGGL((k_coarse_blocks<Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a);
@@ -309,7 +346,8 @@ size_t ws_bytes_coarse(const mrhs_op *op, int n_tv)
 {
     size_t sites = op->Va;
     for (int mu = 0; mu < 4; ++mu) sites += op->Va / op->g.agg[mu];
-    return sizeof(float) * 2 * (size_t)n_tv * op->n_agg * sites * 24;
+    const size_t cols = (size_t)2 * ((n_tv + op->k.S - 1) / op->k.S) * op->k.S;
+    return sizeof(float) * cols * op->n_agg * sites * 24;
 }
 
 int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, hipStream_t st)

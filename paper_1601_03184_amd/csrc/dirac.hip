@@ -37,7 +37,10 @@ __global__ void __launch_bounds__(256 * T) k_residual(KGeo g, const double *__re
                                                       const Ts *__restrict__ x, int ntiles, double *__restrict__ part)
 {
     __shared__ double red[16][T][2];
-    const int blk = blockIdx.x % g.nblk, tile = blockIdx.x / g.nblk;
+    // tiles of one block on one XCD, consecutively: the block's FP64 fields and its
+    // neighbours' spinors are fetched into that XCD's L2 once for all its tiles
+    const int li = xcd_remap(blockIdx.x, g.nblk * ntiles);
+    const int blk = li / ntiles, tile = li - blk * ntiles;
     const int off = threadIdx.x / T, t = threadIdx.x % T;
     const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
     double num = 0, den = 0;
@@ -131,19 +134,26 @@ int dirac_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const v
     return hip_check(hipGetLastError(), "k_dirac launch");
 }
 
-template <typename Ts>
-int residual_dispatch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
+template <typename Ts, int T>
+int residual_launch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
 {
     const KGeo &g = op->k;
-    constexpr int T = 1;
     const int ngrp = (n_rhs + g.S - 1) / g.S;
-    const int ntiles = ngrp * g.S;
+    const int ntiles = ngrp * (g.S / T);
     double *part = (double *)ws;
     hipLaunchKernelGGL((k_residual<Ts, T>), dim3(g.nblk * ntiles), dim3(round64(g.Vb * T)), 0, st, g, op->links64,
                        op->clover64, op->blk_coords, op->loc_coords, (const Ts *)b, (const Ts *)x, ntiles, part);
     if (int rc = hip_check(hipGetLastError(), "k_residual launch")) return rc;
     hipLaunchKernelGGL((k_residual_finish<T>), dim3(n_rhs), dim3(256), 0, st, part, g.nblk, n_rhs, out);
     return hip_check(hipGetLastError(), "k_residual_finish launch");
+}
+
+// two lanes per site (the FP64 stencil needs ~150 VGPRs, so four lanes would spill)
+template <typename Ts>
+int residual_dispatch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
+{
+    if (op->k.S % 2 == 0 && op->k.Vb * 2 <= 512) return residual_launch<Ts, 2>(op, b, x, n_rhs, out, ws, st);
+    return residual_launch<Ts, 1>(op, b, x, n_rhs, out, ws, st);
 }
 
 }  // namespace

@@ -112,7 +112,7 @@ __global__ void k_build_fields(KGeo g, const double *__restrict__ Ucanon, const 
     for (int mu = 0; mu < 4; ++mu) {
         // kernel layout stores W = -U/2 (exact), the hop coefficient folded in
         const double *p = Ucanon + ((long)mu * g.V + cx) * 18;
-        for (int c = 0; c < 18; ++c) links[((long)mu * 18 + c) * g.V + ns] = -0.5 * p[c];
+        for (int c = 0; c < 18; ++c) links[(ns * 4 + mu) * 18 + c] = -0.5 * p[c];
     }
     // F_munu = Q_munu - Q_munu^dag for the 6 planes
     M3 F[6];
@@ -162,7 +162,7 @@ __global__ void k_build_fields(KGeo g, const double *__restrict__ Ucanon, const 
                 }
             }
         }
-        for (int c = 0; c < 36; ++c) clover[(long)(36 * hf + c) * g.V + ns] = out[c];
+        for (int c = 0; c < 36; ++c) clover[ns * 72 + 36 * hf + c] = out[c];
     }
 }
 

@@ -1,30 +1,43 @@
 // gs.hip -- block Gram-Schmidt of the test vectors per aggregate and spin half (the
-// setup of R = Q^dag and P = Q, Sec. 2; the blocks R^h_i of Alg. 3), in FP64.
+// setup of R = Q^dag and P = Q, Sec. 2; the blocks R^h_i of Alg. 3), in FP64 on the
+// matrix cores.
 //
-// One workgroup per (aggregate i, half h).  V^h_i has 6 Va rows (local site, spin in the
-// half, colour) and n_tv columns.  CholQR2: G = V^dag V, G = R1^dag R1 (Cholesky),
-// Q1 = V R1^-1; G2 = Q1^dag Q1 = R2^dag R2; Q = V (R1^-1 R2^-1).  The result is the thin
-// QR factor with a real positive triangular diagonal, the same Q that Gram-Schmidt with
-// re-orthogonalisation produces.  Rows stream through LDS in chunks of CH rows; the
-// n_tv x n_tv matrices stay in LDS.  The three passes read V three times.
+// One workgroup (4 wavefronts) per (aggregate i, half h).  V^h_i has 6 Va rows (local site,
+// spin in the half, colour) and n_tv <= 32 columns, padded to NP = 16 or 32.  CholQR2:
+//   G1 = V^dag V = R1^dag R1,  Q1 = V R1^-1,  G2 = Q1^dag Q1 = R2^dag R2,  Q = V (R1^-1 R2^-1),
+// the thin QR factor with a real positive triangular diagonal (the Q that Gram-Schmidt
+// with re-orthogonalisation produces).  The products V^dag V, V M and Q1^dag Q1 run on
+// v_mfma_f64_16x16x4f64 (16x16 output tiles, complex = 4 real products); the Cholesky
+// factorisations and triangular inverses of the n_tv x n_tv matrices run on the vector
+// units in LDS.
+//
+// MFMA lane layout (16x16x4): lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4(l/16)+r][l%16] in accumulator register r.  A Gram matrix is a sum over rows, so the
+// accumulator of a 16-row transform (rows 4(l/16)+r) is used directly as the operand of
+// the next Gram product, with register r as the K step.
 #include <climits>
 
 #include "internal.h"
 
 namespace {
 
-constexpr int CH = 16;     // rows per chunk
-constexpr int NTHR = 256;
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int NTHR = 256;  // 4 wavefronts
+constexpr int NW = NTHR / 64;
 
 struct GsArgs {
     KGeo g;
-    int Va, n_tv;
+    int Va, n_tv, NT;  // NT = NP / 16 column tiles
     const int32_t *agg_sites;
     const void *V;
     int vdt;
     void *Q;
     int qdt;
     int32_t *status;
+};
+
+struct Cplx {
+    double re, im;
 };
 
 __device__ inline double load_elem(const void *p, int dt, size_t i)
@@ -40,87 +53,91 @@ __device__ inline void store_elem(void *p, int dt, size_t i, double v)
     else ((float *)p)[i] = (float)v;
 }
 
-// native element index of (row n of half h of aggregate i, column k), real part;
-// the imaginary part is one component stride further
-__device__ inline size_t row_index(const GsArgs &a, int i, int h, int n, int k)
+// native element offset of row n of half h of aggregate i (column part excluded), real part
+__device__ inline size_t row_offset(const GsArgs &a, int i, int h, int n)
 {
     const KGeo &g = a.g;
     const int ls = n / 6, sp = (n % 6) / 3, c = n % 3;
     const int ns = a.agg_sites[(size_t)i * a.Va + ls];
     const int blk = ns / g.Vb, off = ns - blk * g.Vb;
     const int r = 2 * (3 * (2 * h + sp) + c);
-    const int grp = k / g.S, t = k - grp * g.S;
-    return ((((size_t)grp * g.nblk + blk) * 24 + r) * g.Vb + off) * g.S + t;
+    return (((size_t)blk * 24 + r) * g.Vb + off) * g.S;
 }
 
-struct Cplx {
-    double re, im;
-};
+// native element offset of column k (test vector), row part excluded
+__device__ inline size_t col_offset(const GsArgs &a, int k)
+{
+    const int grp = k / a.g.S, t = k - grp * a.g.S;
+    return (size_t)grp * a.g.nblk * 24 * a.g.Vb * a.g.S + t;
+}
 
-// G (upper triangle, in place) -> R with G = R^dag R.  Flags a pivot that falls to
+__device__ inline d4 mfma(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
+
+// G (NP x NP, upper triangle, in place) -> R with G = R^dag R.  Flags a pivot that falls to
 // <= 1e-14 of the column's original squared norm, i.e. T_kk <= 1e-7 ||v_k||: the Gram
 // matrix squares the condition number, so below that level CholQR cannot resolve the
 // column (an exactly dependent column leaves a pivot of order eps ||v_k||^2, of either
-// sign).  A flagged pivot is replaced by 1 so that no NaN or Inf is produced.
-__device__ void cholesky_inplace(Cplx *G, const double *diag0, int N, int *bad)
+// sign).  A flagged pivot is replaced by 1 so that no NaN or Inf is produced.  Padding
+// columns (beyond n_tv) get R = 1 on the diagonal and 0 elsewhere.
+__device__ void cholesky_inplace(Cplx *G, const double *diag0, int N, int NP, int *bad)
 {
-    for (int j = 0; j < N; ++j) {
+    for (int j = 0; j < NP; ++j) {
         __syncthreads();
-        const double piv = G[j * N + j].re;
-        const bool deficient = !(piv > 1e-14 * diag0[j]);
-        const double d = deficient ? 1.0 : sqrt(piv);
+        const double piv = G[j * NP + j].re;
+        const bool pad = j >= N;
+        const bool deficient = !pad && !(piv > 1e-14 * diag0[j]);
+        const double d = (deficient || pad) ? 1.0 : sqrt(piv);
         if (threadIdx.x == 0 && deficient) *bad = 1;
         __syncthreads();
-        for (int l = j + threadIdx.x; l < N; l += blockDim.x) {
-            Cplx v = G[j * N + l];
+        for (int l = j + threadIdx.x; l < NP; l += blockDim.x) {
+            Cplx v = G[j * NP + l];
             if (l == j) v = {d, 0.0};
-            else v = {v.re / d, v.im / d};
-            G[j * N + l] = v;
+            else v = pad ? Cplx{0.0, 0.0} : Cplx{v.re / d, v.im / d};
+            G[j * NP + l] = v;
         }
         __syncthreads();
-        const int m = N - j - 1;
+        const int m = NP - j - 1;
         for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
             const int k = j + 1 + e / m, l = j + 1 + e % m;
             if (l < k) continue;
-            const Cplx rk = G[j * N + k], rl = G[j * N + l];
+            const Cplx rk = G[j * NP + k], rl = G[j * NP + l];
             // G[k][l] -= conj(R[j][k]) R[j][l]
-            G[k * N + l].re -= rk.re * rl.re + rk.im * rl.im;
-            G[k * N + l].im -= rk.re * rl.im - rk.im * rl.re;
+            G[k * NP + l].re -= rk.re * rl.re + rk.im * rl.im;
+            G[k * NP + l].im -= rk.re * rl.im - rk.im * rl.re;
         }
     }
     __syncthreads();
 }
 
-// X = R^-1 for upper-triangular R (both N x N in LDS); one thread per column.
-__device__ void tri_inverse(const Cplx *R, Cplx *X, int N)
+// X = R^-1 for upper-triangular R (NP x NP in LDS); one thread per column.
+__device__ void tri_inverse(const Cplx *R, Cplx *X, int NP)
 {
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) X[e] = {0.0, 0.0};
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) X[e] = {0.0, 0.0};
     __syncthreads();
-    for (int l = threadIdx.x; l < N; l += blockDim.x) {
-        const Cplx rll = R[l * N + l];
-        X[l * N + l] = {1.0 / rll.re, 0.0};
+    for (int l = threadIdx.x; l < NP; l += blockDim.x) {
+        X[l * NP + l] = {1.0 / R[l * NP + l].re, 0.0};
         for (int k = l - 1; k >= 0; --k) {
             double sr = 0, si = 0;
             for (int j = k + 1; j <= l; ++j) {
-                const Cplx r = R[k * N + j], x = X[j * N + l];
+                const Cplx r = R[k * NP + j], x = X[j * NP + l];
                 sr += r.re * x.re - r.im * x.im;
                 si += r.re * x.im + r.im * x.re;
             }
-            const double d = R[k * N + k].re;
-            X[k * N + l] = {-sr / d, -si / d};
+            const double d = R[k * NP + k].re;
+            X[k * NP + l] = {-sr / d, -si / d};
         }
     }
     __syncthreads();
 }
 
-// C = A B for upper-triangular A, B (N x N in LDS)
-__device__ void tri_product(const Cplx *A, const Cplx *B, Cplx *C, int N)
+// C = A B for upper-triangular A, B (NP x NP in LDS)
+__device__ void tri_product(const Cplx *A, const Cplx *B, Cplx *C, int NP)
 {
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int k = e / N, l = e % N;
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+        const int k = e / NP, l = e % NP;
         double sr = 0, si = 0;
         for (int j = k; j <= l; ++j) {
-            const Cplx x = A[k * N + j], y = B[j * N + l];
+            const Cplx x = A[k * NP + j], y = B[j * NP + l];
             sr += x.re * y.re - x.im * y.im;
             si += x.re * y.im + x.im * y.re;
         }
@@ -129,112 +146,168 @@ __device__ void tri_product(const Cplx *A, const Cplx *B, Cplx *C, int N)
     __syncthreads();
 }
 
-// Load rows [r0, r0+CH) of V^h_i into raw[CH][N] (zero beyond the last row)
-__device__ void load_chunk(const GsArgs &a, int i, int h, int r0, int rows, Cplx *raw)
+// Gram accumulators of the tile pairs (0,0), (0,1), (1,1), real and imaginary part
+struct GramAcc {
+    d4 re[3], im[3];
+};
+
+__device__ inline int pair_index(int ti, int tj) { return ti == 0 ? tj : 2; }
+
+// G += x^dag y for one K step, x the operands of the NT column tiles (x = y)
+template <int NT> __device__ inline void gram_step(const double (&xr)[2], const double (&xi)[2], GramAcc &acc)
+{
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj) {
+            const int p = pair_index(ti, tj);
+            acc.re[p] = mfma(xr[ti], xr[tj], acc.re[p]);
+            acc.re[p] = mfma(xi[ti], xi[tj], acc.re[p]);
+            acc.im[p] = mfma(xr[ti], xi[tj], acc.im[p]);
+            acc.im[p] = mfma(-xi[ti], xr[tj], acc.im[p]);
+        }
+}
+
+// write this wavefront's Gram tiles (upper triangle of tiles) to Gw (NP x NP complex)
+template <int NT> __device__ inline void gram_store(const GramAcc &acc, Cplx *Gw, int NP, int lane)
+{
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj) {
+            const int p = pair_index(ti, tj);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ti * 16 + 4 * (lane >> 4) + r, col = tj * 16 + (lane & 15);
+                Gw[row * NP + col] = {acc.re[p][r], acc.im[p][r]};
+            }
+        }
+}
+
+// 16-row block transform: tile tj of (rows b0..b0+15 of V) M for upper-triangular M
+// (NP x NP in LDS).  Lane l supplies V[b0 + l%16][4 ks + l/16] and M[4 ks + l/16][16 tj + l%16].
+template <int NT>
+__device__ inline void transform_block(const GsArgs &a, int i, int h, int b0, int rows, const Cplx *M, int NP, int lane,
+                                       d4 (&dr)[2], d4 (&di)[2])
 {
     const int N = a.n_tv;
+    const int rr = b0 + (lane & 15);
     const size_t cstr = (size_t)a.g.Vb * a.g.S;
-    for (int e = threadIdx.x; e < CH * N; e += blockDim.x) {
-        const int rr = e / N, k = e % N, n = r0 + rr;
-        Cplx v = {0.0, 0.0};
-        if (n < rows) {
-            const size_t idx = row_index(a, i, h, n, k);
-            v = {load_elem(a.V, a.vdt, idx), load_elem(a.V, a.vdt, idx + cstr)};
+    const size_t ro = rr < rows ? row_offset(a, i, h, rr) : 0;
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) dr[tj] = di[tj] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NT * 4; ++ks) {
+        const int k = ks * 4 + (lane >> 4);  // column of V = row of M
+        double vr = 0.0, vi = 0.0;
+        if (rr < rows && k < N) {
+            const size_t idx = ro + col_offset(a, k);
+            vr = load_elem(a.V, a.vdt, idx);
+            vi = load_elem(a.V, a.vdt, idx + cstr);
         }
-        raw[e] = v;
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+            if (ks * 4 >= (tj + 1) * 16) continue;  // M is upper triangular
+            const Cplx m = M[k * NP + tj * 16 + (lane & 15)];
+            dr[tj] = mfma(vr, m.re, dr[tj]);
+            dr[tj] = mfma(-vi, m.im, dr[tj]);
+            di[tj] = mfma(vr, m.im, di[tj]);
+            di[tj] = mfma(vi, m.re, di[tj]);
+        }
     }
 }
 
-// out[CH][N] = raw[CH][N] M, M upper triangular
-__device__ void transform_chunk(const Cplx *raw, const Cplx *M, Cplx *out, int N)
-{
-    for (int e = threadIdx.x; e < CH * N; e += blockDim.x) {
-        const int rr = e / N, l = e % N;
-        double sr = 0, si = 0;
-        for (int j = 0; j <= l; ++j) {
-            const Cplx v = raw[rr * N + j], m = M[j * N + l];
-            sr += v.re * m.re - v.im * m.im;
-            si += v.re * m.im + v.im * m.re;
-        }
-        out[e] = {sr, si};
-    }
-}
-
-// G[k][l] += sum_rows conj(C[r][k]) C[r][l] for k <= l
-__device__ void gram_accumulate(const Cplx *C, Cplx *G, int N)
-{
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-        const int k = e / N, l = e % N;
-        if (l < k) continue;
-        double sr = 0, si = 0;
-#pragma unroll 4
-        for (int rr = 0; rr < CH; ++rr) {
-            const Cplx x = C[rr * N + k], y = C[rr * N + l];
-            sr += x.re * y.re + x.im * y.im;
-            si += x.re * y.im - x.im * y.re;
-        }
-        G[e].re += sr;
-        G[e].im += si;
-    }
-}
-
-__global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
+template <int NT> __global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NP = NT * 16;
     const int N = a.n_tv;
-    Cplx *G = reinterpret_cast<Cplx *>(smem);  // N*N
-    Cplx *X1 = G + N * N;                      // R1^-1, later R1^-1 R2^-1
-    Cplx *X2 = X1 + N * N;                     // R2^-1
-    Cplx *raw = X2 + N * N;                    // CH*N
-    Cplx *tr = raw + CH * N;                   // CH*N
-    double *diag0 = reinterpret_cast<double *>(tr + CH * N);  // N
+    Cplx *Gp = reinterpret_cast<Cplx *>(smem);  // [NW][NP*NP] partial Gram matrices
+    Cplx *G = Gp + NW * NP * NP;                // reduced Gram matrix / Cholesky factor / M
+    Cplx *X1 = G + NP * NP;                     // R1^-1
+    Cplx *X2 = X1 + NP * NP;                    // R2^-1
+    double *diag0 = reinterpret_cast<double *>(X2 + NP * NP);
     __shared__ int bad;
 
     const int i = blockIdx.x >> 1, h = blockIdx.x & 1;
     const int rows = 6 * a.Va;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const size_t cstr = (size_t)a.g.Vb * a.g.S;
     if (threadIdx.x == 0) bad = 0;
 
     for (int pass = 0; pass < 2; ++pass) {
-        for (int e = threadIdx.x; e < N * N; e += blockDim.x) G[e] = {0.0, 0.0};
-        for (int r0 = 0; r0 < rows; r0 += CH) {
-            __syncthreads();
-            load_chunk(a, i, h, r0, rows, raw);
-            __syncthreads();
-            if (pass == 0) {
-                gram_accumulate(raw, G, N);
-            } else {
-                transform_chunk(raw, X1, tr, N);
-                __syncthreads();
-                gram_accumulate(tr, G, N);
+        GramAcc acc;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
+        if (pass == 0) {
+            // G1 = V^dag V: K steps of 4 rows, spread over the wavefronts
+            size_t co[2] = {0, 0};
+#pragma unroll
+            for (int t = 0; t < NT; ++t) co[t] = col_offset(a, t * 16 + (lane & 15));
+            const int nsteps = (rows + 3) / 4;
+            for (int s = wave; s < nsteps; s += NW) {
+                const int n = s * 4 + (lane >> 4);
+                double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
+                if (n < rows) {
+                    const size_t ro = row_offset(a, i, h, n);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        if (t * 16 + (lane & 15) < N) {
+                            xr[t] = load_elem(a.V, a.vdt, ro + co[t]);
+                            xi[t] = load_elem(a.V, a.vdt, ro + co[t] + cstr);
+                        }
+                }
+                gram_step<NT>(xr, xi, acc);
+            }
+        } else {
+            // G2 = Q1^dag Q1, Q1 = V R1^-1 formed 16 rows at a time on the matrix cores
+            for (int b0 = wave * 16; b0 < rows; b0 += NW * 16) {
+                d4 dr[2], di[2];
+                transform_block<NT>(a, i, h, b0, rows, X1, NP, lane, dr, di);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double xr[2] = {dr[0][r], dr[1][r]};
+                    const double xi[2] = {di[0][r], di[1][r]};
+                    gram_step<NT>(xr, xi, acc);
+                }
             }
         }
+        gram_store<NT>(acc, Gp + wave * NP * NP, NP, lane);
         __syncthreads();
-        if (pass == 0)
-            for (int k = threadIdx.x; k < N; k += blockDim.x) diag0[k] = G[k * N + k].re;
-        else
-            for (int k = threadIdx.x; k < N; k += blockDim.x) diag0[k] = 1.0;
-        cholesky_inplace(G, diag0, N, &bad);
-        if (pass == 0) {
-            tri_inverse(G, X1, N);
-        } else {
-            tri_inverse(G, X2, N);
-            tri_product(X1, X2, G, N);  // G <- R1^-1 R2^-1
+        // reduce the wavefronts' partial Gram matrices (upper triangle)
+        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
+            const int k = e / NP, l = e % NP;
+            if (l < k) continue;
+            Cplx s = Gp[e];
+            for (int w = 1; w < NW; ++w) {
+                s.re += Gp[w * NP * NP + e].re;
+                s.im += Gp[w * NP * NP + e].im;
+            }
+            G[e] = s;
         }
+        __syncthreads();
+        for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = pass == 0 ? G[k * NP + k].re : 1.0;
+        cholesky_inplace(G, diag0, N, NP, &bad);
+        tri_inverse(G, pass == 0 ? X1 : X2, NP);
     }
-    // Q = V (R1^-1 R2^-1)
-    for (int r0 = 0; r0 < rows; r0 += CH) {
-        __syncthreads();
-        load_chunk(a, i, h, r0, rows, raw);
-        __syncthreads();
-        transform_chunk(raw, G, tr, N);
-        __syncthreads();
-        for (int e = threadIdx.x; e < CH * N; e += blockDim.x) {
-            const int rr = e / N, k = e % N, n = r0 + rr;
+    tri_product(X1, X2, G, NP);  // G <- R1^-1 R2^-1
+    // Q = V (R1^-1 R2^-1), 16-row blocks spread over the wavefronts
+    for (int b0 = wave * 16; b0 < rows; b0 += NW * 16) {
+        d4 dr[2], di[2];
+        transform_block<NT>(a, i, h, b0, rows, G, NP, lane, dr, di);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = b0 + 4 * (lane >> 4) + r;
             if (n >= rows) continue;
-            const size_t idx = row_index(a, i, h, n, k);
-            store_elem(a.Q, a.qdt, idx, tr[e].re);
-            store_elem(a.Q, a.qdt, idx + cstr, tr[e].im);
+            const size_t ro = row_offset(a, i, h, n);
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj) {
+                const int k = tj * 16 + (lane & 15);
+                if (k >= N) continue;
+                const size_t idx = ro + col_offset(a, k);
+                store_elem(a.Q, a.qdt, idx, dr[tj][r]);
+                store_elem(a.Q, a.qdt, idx + cstr, di[tj][r]);
+            }
         }
     }
     __syncthreads();
@@ -247,7 +320,23 @@ __global__ void k_status_final(int32_t *s)
     if (*s == INT_MAX) *s = 0;
 }
 
-size_t gs_lds(int N) { return sizeof(Cplx) * (3 * (size_t)N * N + 2 * (size_t)CH * N) + sizeof(double) * N; }
+size_t gs_lds(int NP) { return sizeof(Cplx) * (size_t)(NW + 3) * NP * NP + sizeof(double) * NP; }
+
+template <int NT> int launch_nt(const GsArgs &a, int n_agg, size_t max_lds, hipStream_t st)
+{
+    const size_t lds = gs_lds(NT * 16);
+    if (lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "Gram-Schmidt LDS exceeds the workgroup limit");
+    static size_t done = 0;
+    if (lds > 65536 && lds > done) {
+        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_block_gs<NT>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                               "hipFuncSetAttribute(gs LDS)"))
+            return rc;
+        done = lds;
+    }
+    hipLaunchKernelGGL(k_block_gs<NT>, dim3(2 * n_agg), dim3(NTHR), lds, st, a);
+    return hip_check(hipGetLastError(), "k_block_gs launch");
+}
 
 }  // namespace
 
@@ -256,34 +345,28 @@ size_t ws_bytes_gs(const mrhs_op *, int) { return 0; }
 int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *,
               hipStream_t st)
 {
-    const size_t lds = gs_lds(n_tv);
-    if (lds > op->max_lds) return set_error(MRHS_EUNSUPPORTED, "too many test vectors for the Gram-Schmidt LDS");
-    static size_t done = 0;
-    if (lds > 65536 && lds > done) {
-        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_block_gs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)lds), "hipFuncSetAttribute(gs LDS)"))
-            return rc;
-        done = lds;
-    }
+    if (n_tv > 32) return set_error(MRHS_EUNSUPPORTED, "Gram-Schmidt handles at most 32 test vectors");
     GsArgs a{};
     a.g = op->k;
     a.Va = op->Va;
     a.n_tv = n_tv;
+    a.NT = n_tv > 16 ? 2 : 1;
     a.agg_sites = op->agg_sites;
     a.V = V;
     a.vdt = vdt;
     a.Q = Q;
     a.qdt = qdt;
     a.status = status;
+    if (!a.agg_sites || !a.V || !a.Q) return set_error(MRHS_EINVAL, "block_orthonormalize: missing buffer");
     if (status) {
         hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, st, status);
         if (int rc = hip_check(hipGetLastError(), "k_status_init launch")) return rc;
     }
-    hipLaunchKernelGGL(k_block_gs, dim3(2 * op->n_agg), dim3(NTHR), lds, st, a);
-    if (int rc = hip_check(hipGetLastError(), "k_block_gs launch")) return rc;
+    int rc = a.NT == 2 ? launch_nt<2>(a, op->n_agg, op->max_lds, st) : launch_nt<1>(a, op->n_agg, op->max_lds, st);
+    if (rc) return rc;
     if (status) {
         hipLaunchKernelGGL(k_status_final, dim3(1), dim3(1), 0, st, status);
-        if (int rc = hip_check(hipGetLastError(), "k_status_final launch")) return rc;
+        if (int rc2 = hip_check(hipGetLastError(), "k_status_final launch")) return rc2;
     }
     return MRHS_OK;
 }

@@ -38,7 +38,7 @@ struct mrhs_op {
     int na[4];   // aggregates per direction
     int Va;      // aggregate volume
     int n_agg;
-    // fields in kernel layout: links [4][18][V], clover [72][V] (native site order)
+    // fields in kernel layout: links [V][4][18], clover [V][72] (native site order)
     double *links64 = nullptr, *clover64 = nullptr;
     float *links32 = nullptr, *clover32 = nullptr;
     uint32_t *blk_coords = nullptr;  // [nblk]
@@ -138,8 +138,11 @@ __device__ inline void hop_accumulate(const T (&U)[18], const Spinor<T> &chi, Sp
                 T ur, ui;
                 if constexpr (DAG) { ur = U[2 * (3 * c + a)]; ui = -U[2 * (3 * c + a) + 1]; }
                 else { ur = U[2 * (3 * a + c)]; ui = U[2 * (3 * a + c) + 1]; }
-                sr += ur * hre[r][c] - ui * him[r][c];
-                si += ur * him[r][c] + ui * hre[r][c];
+                // one product per statement so that each contracts into an FMA
+                sr += ur * hre[r][c];
+                sr -= ui * him[r][c];
+                si += ur * him[r][c];
+                si += ui * hre[r][c];
             }
             wre[r][a] = sr;
             wim[r][a] = si;
@@ -177,8 +180,10 @@ template <int HF, typename T> __device__ inline void clover_half(const T (&cl)[3
             const int kidx = a * 5 - a * (a - 1) / 2 + (bb - a - 1);  // index of pair (a,bb), a<bb
             T ur = cl[6 + 2 * kidx], ui = cl[7 + 2 * kidx];
             if (i > j) ui = -ui;  // lower triangle: conjugate
-            sr += ur * psi.re[o + j] - ui * psi.im[o + j];
-            si += ur * psi.im[o + j] + ui * psi.re[o + j];
+            sr += ur * psi.re[o + j];
+            sr -= ui * psi.im[o + j];
+            si += ur * psi.im[o + j];
+            si += ui * psi.re[o + j];
         }
         out.re[o + i] = sr;
         out.im[o + i] = si;
@@ -229,19 +234,36 @@ __device__ inline long vec_index(const KGeo &k, int grp, int blk, int r, int off
     return (((long)grp * k.nblk + blk) * 24 + r) * (long)k.Vb * k.S + (long)off * k.S + t;
 }
 
-template <typename Tf, typename T> __device__ inline void load_link(const Tf *__restrict__ links, long V, int mu, long site, T (&U)[18])
+// Fields are stored site by site in native site order: links [V][4][18] (the 4 forward
+// links of a site, 18 reals each, pre-scaled by -1/2), clover [V][72].  A lane loads a
+// link or a clover half from one address with immediate offsets (64/128-bit loads).
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename Tf, typename T> __device__ inline void load_link(const Tf *__restrict__ links, long, int mu, long site, T (&U)[18])
 {
-    const uint32_t s = (uint32_t)site;
+    using V2 = typename Vec2<Tf>::type;
+    const V2 *p = reinterpret_cast<const V2 *>(links + ((size_t)(uint32_t)site * 4 + mu) * 18);
 #pragma unroll
-    for (int c = 0; c < 18; ++c) U[c] = (T)(links + (size_t)(mu * 18 + c) * V)[s];
+    for (int c = 0; c < 9; ++c) {
+        const V2 v = p[c];
+        U[2 * c] = (T)v.x;
+        U[2 * c + 1] = (T)v.y;
+    }
 }
 
 template <int HF, typename Tf, typename T>
-__device__ inline void load_clover_half(const Tf *__restrict__ cl, long V, long site, T (&A)[36])
+__device__ inline void load_clover_half(const Tf *__restrict__ cl, long, long site, T (&A)[36])
 {
-    const uint32_t s = (uint32_t)site;
+    using V2 = typename Vec2<Tf>::type;
+    const V2 *p = reinterpret_cast<const V2 *>(cl + (size_t)(uint32_t)site * 72 + 36 * HF);
 #pragma unroll
-    for (int c = 0; c < 36; ++c) A[c] = (T)(cl + (size_t)(36 * HF + c) * V)[s];
+    for (int c = 0; c < 18; ++c) {
+        const V2 v = p[c];
+        A[2 * c] = (T)v.x;
+        A[2 * c + 1] = (T)v.y;
+    }
 }
 
 // Launchers (defined in the kernel files)

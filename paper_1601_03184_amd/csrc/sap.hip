@@ -30,24 +30,44 @@ template <typename Ts, typename Tc> struct SapArgs {
     Ts *x;
 };
 
-// q = D_j rho at site off for lane t, rho read from LDS; hops leaving the block dropped.
-template <int MU, typename Tc>
-__device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, const Tc *rho_s, int T, int blk, int off,
-                                  int t, const int (&lc)[4], Spinor<Tc> &q)
+// The block residual rho lives in LDS as (re, im) pairs, [12][Vb][T]: lane (off, t)
+// reads component c at (c * Vb + off) * T + t, consecutive lanes consecutive pairs.
+template <typename Tc> struct LdsPair;
+template <> struct LdsPair<float> { using type = float2; };
+template <> struct LdsPair<double> { using type = double2; };
+
+template <typename Tc>
+__device__ inline void lds_load(const typename LdsPair<Tc>::type *rho, int str, int idx, Spinor<Tc> &s)
 {
-    const long ns = (long)blk * g.Vb + off;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const auto v = rho[c * str + idx];
+        s.re[c] = v.x;
+        s.im[c] = v.y;
+    }
+}
+
+template <typename Tc>
+__device__ inline void lds_store(typename LdsPair<Tc>::type *rho, int str, int idx, const Spinor<Tc> &s)
+{
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rho[c * str + idx] = {s.re[c], s.im[c]};
+}
+
+// q += hops of D_j rho at site off (lane t), rho from LDS; hops leaving the block dropped.
+// ns is the site's native index (opaque to the compiler, so the link loads stay inside
+// the MR loop).
+template <int MU, typename Tc>
+__device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, const typename LdsPair<Tc>::type *rho,
+                                  int T, int ns, int off, int t, const int (&lc)[4], Spinor<Tc> &q)
+{
     const int str = g.Vb * T;
     int noff = -1;
     if (lc[MU] + 1 < g.b[MU]) noff = off + g.ostr[MU];
     else if (g.nb[MU] == 1) noff = off - (g.b[MU] - 1) * g.ostr[MU];
     if (noff >= 0) {
         Spinor<Tc> chi;
-        const Tc *p = rho_s + noff * T + t;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            chi.re[c] = p[(2 * c) * str];
-            chi.im[c] = p[(2 * c + 1) * str];
-        }
+        lds_load<Tc>(rho, str, noff * T + t, chi);
         Tc U[18];
         load_link(links, g.V, MU, ns, U);
         hop_accumulate<MU, -1, false>(U, chi, q);
@@ -58,14 +78,9 @@ __device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, c
     else if (g.nb[MU] == 1) noff = off + (g.b[MU] - 1) * g.ostr[MU];
     if (noff >= 0) {
         Spinor<Tc> chi;
-        const Tc *p = rho_s + noff * T + t;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            chi.re[c] = p[(2 * c) * str];
-            chi.im[c] = p[(2 * c + 1) * str];
-        }
+        lds_load<Tc>(rho, str, noff * T + t, chi);
         Tc U[18];
-        load_link(links, g.V, MU, (long)blk * g.Vb + noff, U);
+        load_link(links, g.V, MU, ns + (noff - off), U);
         hop_accumulate<MU, +1, true>(U, chi, q);
     }
 }
@@ -73,11 +88,12 @@ __device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, c
 template <typename Ts, typename Tc, int T>
 __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
 {
+    using P2 = typename LdsPair<Tc>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const KGeo &g = a.g;
-    Tc *rho_s = reinterpret_cast<Tc *>(smem);
+    P2 *rho = reinterpret_cast<P2 *>(smem);
     const int str = g.Vb * T;
-    Tc *red_s = rho_s + 24 * str;  // [waves][T][3]
+    Tc *red_s = reinterpret_cast<Tc *>(rho + 12 * str);  // [waves][T][3]
 
     const int nwg = a.nblocks * a.ntiles;
     const int li = xcd_remap(blockIdx.x, nwg);
@@ -86,6 +102,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
     const int off = threadIdx.x / T, t = threadIdx.x % T;
     const bool active = off < g.Vb;
     const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
+    const int me = off * T + t;                                   // this lane's LDS slot
     int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
     if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
 
@@ -107,12 +124,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
         } else {
             load_spinor<Tc>(g, a.b, grp, blk, off, tt, r);
         }
-        Tc *p = rho_s + off * T + t;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            p[(2 * c) * str] = r.re[c];
-            p[(2 * c + 1) * str] = r.im[c];
-        }
+        lds_store<Tc>(rho, str, me, r);
     }
 
     // 2. minimal residual on the block operator
@@ -123,35 +135,33 @@ __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
         __syncthreads();
         Spinor<Tc> q;
         Tc qq = 0, qrr = 0, qri = 0;
-        // reload the block's fields from cache in every step rather than keeping
-        // 216 of them in registers across the loop
-        const Tc *links = opaque_ptr(a.links), *clover = opaque_ptr(a.clover);
         if (active) {
-            const Tc *p = rho_s + off * T + t;
+            // the site index is hidden from the compiler so that the block's fields are
+            // re-read from cache in every step instead of held in registers across the loop
+            const int ns = opaque_index(blk * g.Vb + off);
             {
                 Spinor<Tc> own;
-#pragma unroll
-                for (int c = 0; c < 12; ++c) {
-                    own.re[c] = p[(2 * c) * str];
-                    own.im[c] = p[(2 * c + 1) * str];
-                }
-                clover_site(clover, g.V, (long)blk * g.Vb + off, own, q);
+                lds_load<Tc>(rho, str, me, own);
+                clover_site(a.clover, g.V, ns, own, q);
             }
             hop_fence(q);
-            block_hops<0>(g, links, rho_s, T, blk, off, t, lc, q);
+            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, q);
             hop_fence(q);
-            block_hops<1>(g, links, rho_s, T, blk, off, t, lc, q);
+            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, q);
             hop_fence(q);
-            block_hops<2>(g, links, rho_s, T, blk, off, t, lc, q);
+            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, q);
             hop_fence(q);
-            block_hops<3>(g, links, rho_s, T, blk, off, t, lc, q);
+            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, q);
             hop_fence(q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const Tc orr = p[(2 * c) * str], ori = p[(2 * c + 1) * str];
-                qq += q.re[c] * q.re[c] + q.im[c] * q.im[c];
-                qrr += q.re[c] * orr + q.im[c] * ori;
-                qri += q.re[c] * ori - q.im[c] * orr;
+                const P2 o = rho[c * str + me];
+                qq += q.re[c] * q.re[c];
+                qq += q.im[c] * q.im[c];
+                qrr += q.re[c] * o.x;
+                qrr += q.im[c] * o.y;
+                qri += q.re[c] * o.y;
+                qri -= q.im[c] * o.x;
             }
         } else {
             spinor_zero(q);
@@ -174,14 +184,19 @@ __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
         const Tc ar = sqq > Tc(0) ? sr / sqq : Tc(0);
         const Tc ai = sqq > Tc(0) ? si / sqq : Tc(0);
         if (active) {
-            Tc *p = rho_s + off * T + t;
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
-                const Tc rr = p[(2 * c) * str], ri = p[(2 * c + 1) * str];
-                e.re[c] += ar * rr - ai * ri;
-                e.im[c] += ar * ri + ai * rr;
-                p[(2 * c) * str] = rr - (ar * q.re[c] - ai * q.im[c]);
-                p[(2 * c + 1) * str] = ri - (ar * q.im[c] + ai * q.re[c]);
+                const P2 o = rho[c * str + me];
+                e.re[c] += ar * o.x;
+                e.re[c] -= ai * o.y;
+                e.im[c] += ar * o.y;
+                e.im[c] += ai * o.x;
+                Tc nr = o.x, ni = o.y;
+                nr -= ar * q.re[c];
+                nr += ai * q.im[c];
+                ni -= ar * q.im[c];
+                ni -= ai * q.re[c];
+                rho[c * str + me] = {nr, ni};
             }
         }
     }
@@ -230,7 +245,7 @@ template <typename Ts, typename Tc, int T> int launch_half(const SapArgs<Ts, Tc>
 {
     const KGeo &g = a.g;
     const int threads = round64(g.Vb * T);
-    const size_t lds = sizeof(Tc) * (24 * (size_t)g.Vb * T + (size_t)(threads / 64) * T * 3);
+    const size_t lds = sizeof(Tc) * (24 * (size_t)g.Vb * T + (size_t)(threads / 64) * T * 3);  // rho pairs + reductions
     if (lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "SAP tile exceeds the LDS of a workgroup");
     if (int rc = set_lds<Ts, Tc, T>(lds)) return rc;
     hipLaunchKernelGGL((k_sap_half<Ts, Tc, T>), dim3(a.nblocks * a.ntiles), dim3(threads), lds, st, a);

@@ -20,12 +20,12 @@ template <typename T> __device__ inline void value_fence(Spinor<T> &s)
     for (int c = 0; c < 12; ++c) asm volatile("" : "+v"(s.re[c]), "+v"(s.im[c]));
 }
 
-// Hide a uniform pointer from loop-invariant code motion: the loads through it are then
-// issued inside the loop instead of being hoisted (and held in registers) above it.
-template <typename P> __device__ inline P opaque_ptr(P p)
+// Hide a per-lane index from loop-invariant code motion: loads addressed through it
+// are issued inside the loop instead of being hoisted (and held in registers) above it.
+__device__ inline int opaque_index(int i)
 {
-    asm volatile("" : "+s"(p));
-    return p;
+    asm volatile("" : "+v"(i));
+    return i;
 }
 
 template <typename T> __device__ inline void hop_fence(Spinor<T> &s)
