@@ -152,6 +152,48 @@ def time_call(fn, reps, warmup=2):
     return a.elapsed_time(b) / reps
 
 
+BATCH = [([8, 8, 8, 8], 401, 8), ([12, 12, 12, 12], 411, 16), ([16, 16, 16, 32], 421, 24), ([24, 24, 24, 48], 431, 32)]
+
+
+def batched_bench(reps=5):
+    """Uneven lattices, each with its own test vectors, FP32, 3 x 4: one batched call (one
+    launch per half-sweep for all four), the same work as four separate calls, and the
+    batched call replayed from a captured graph."""
+    ops, bs, xs, ns, upd = [], [], [], [], 0
+    for (Lb, seed, n) in BATCH:
+        U = inputs.gauge_field(Lb, SIGMA, seed)
+        v = inputs.test_vectors(Lb, n, seed + 1)
+        op = mrhs.Operator(Lb, BLOCK, BLOCK, torch.from_numpy(U), M0, CSW, prec=mrhs.PREC_F32, short_len=4)
+        ops.append(op)
+        bs.append(op.pack(torch.from_numpy(v)))
+        xs.append(op.empty(n))
+        ns.append(n)
+        upd += int(np.prod(Lb)) * n * N_SAP
+    handles = [op.handle for op in ops]
+    ws = torch.empty(max(256, mrhs.mrhs_batched_workspace_bytes(handles, ns)), dtype=torch.uint8, device="cuda")
+    wss = [op.workspace(n) for op, n in zip(ops, ns)]
+    batched = lambda: mrhs.sap_smooth_mrhs_batched(handles, bs, xs, ns, N_SAP, N_MR, ws)
+    t_b = time_call(batched, reps)
+
+    def seq():
+        for op, b, x, n, w in zip(ops, bs, xs, ns, wss):
+            mrhs.sap_smooth_mrhs(op.handle, b, x, n, N_SAP, N_MR, w)
+    t_s = time_call(seq, reps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            mrhs.sap_smooth_mrhs_batched(handles, bs, xs, ns, N_SAP, N_MR, ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    t_g = time_call(g.replay, reps)
+    for op in ops:
+        op.close()
+    return {"lattices": [b[0] for b in BATCH], "n_tv": ns, "site_rhs_updates": upd,
+            "batched_ms": round(t_b, 4), "separate_calls_ms": round(t_s, 4), "graph_replay_ms": round(t_g, 4),
+            "batched_updates_per_s": upd / (t_b * 1e-3), "graph_updates_per_s": upd / (t_g * 1e-3)}
+
+
 def cpu_baseline(U, v, x_gpu, budget_s=30.0):
     """The oracle on the host cores: SAP on a sample of test vectors (they are independent),
     Gram-Schmidt on all aggregates, D_c on a sample of aggregates; scaled to the full step."""
@@ -197,6 +239,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-srhs", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -265,6 +308,12 @@ def main():
         s1.op.close()
         m64.op.close()
 
+    batched = None
+    if not args.no_batched:
+        log("batched uneven lattices")
+        batched = batched_bench()
+        log("batched %s" % batched)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
@@ -294,6 +343,7 @@ def main():
         "stencil_roofline": stencil,
         "sap": sap_info,
         "srhs": srhs,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     mr.op.close()

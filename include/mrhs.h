@@ -146,6 +146,21 @@ int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void
 int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* SAP on several operators at once -- lattices of uneven size, each with its own
+ * right-hand sides -- with one launch per half-sweep for the whole batch (the loop over
+ * test vectors and over lattices moved into the kernel, Sec. 3).  The enqueued work is a
+ * fixed sequence of kernels whose arguments carry everything by value, so the call can be
+ * captured into a graph and replayed.  ops, b, x, n_rhs: HOST arrays of n_inst (1..8)
+ * entries; ops[k] share precision and short length; b[k], x[k] are DEVICE native vectors
+ * of ops[k] for n_rhs[k] right-hand sides, no two overlapping.  The result for instance k
+ * equals sap_smooth_mrhs(ops[k], b[k], x[k], n_rhs[k], n_sap, n_mr) with the batch's tile
+ * (the smallest of the operators' SAP tiles).  ws: at least
+ * mrhs_batched_workspace_bytes(ops, n_inst, n_rhs) bytes. */
+int sap_smooth_mrhs_batched(mrhs_op *const *ops, int32_t n_inst, const void *const *b, void *const *x,
+                            const int32_t *n_rhs, int32_t n_sap, int32_t n_mr, void *ws, size_t ws_bytes,
+                            void *stream);
+size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const int32_t *n_rhs);
+
 /* Execution tiles (right-hand sides per workgroup) of the SAP and stencil kernels; 0 keeps
  * the current choice.  A tile must divide the op's short length and fit the block. */
 int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile);

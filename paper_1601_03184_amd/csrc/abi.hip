@@ -363,6 +363,39 @@ int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n
     return launch_coarse(op, Q, q_dtype, n_tv, Dc, ws, (hipStream_t)stream);
 }
 
+size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const int32_t *n_rhs)
+{
+    if (!ops || !n_rhs || n_inst <= 0) return 0;
+    for (int k = 0; k < n_inst; ++k)
+        if (!ops[k] || n_rhs[k] <= 0) return 0;
+    return std::max(ws_bytes_sap_batched(ops, n_inst, n_rhs), (size_t)256);
+}
+
+int sap_smooth_mrhs_batched(mrhs_op *const *ops, int32_t n_inst, const void *const *b, void *const *x,
+                            const int32_t *n_rhs, int32_t n_sap, int32_t n_mr, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    if (!ops || !b || !x || !n_rhs) return set_error(MRHS_EINVAL, "null argument");
+    if (n_inst <= 0 || n_inst > 8) return set_error(MRHS_EINVAL, "n_inst must be 1..8");
+    if (n_sap < 0 || n_mr < 0) return set_error(MRHS_EINVAL, "negative iteration count");
+    for (int k = 0; k < n_inst; ++k) {
+        if (int rc = check_op(ops[k])) return rc;
+        if (int rc = check_nrhs(n_rhs[k])) return rc;
+        if (!b[k] || !x[k]) return set_error(MRHS_EINVAL, "null vector");
+        if (ops[k]->prec != ops[0]->prec || ops[k]->k.S != ops[0]->k.S)
+            return set_error(MRHS_EINVAL, "all operators of a batch need the same precision and short length");
+        const size_t bytes = native_elems(ops[k], n_rhs[k]) * dtype_size(ops[k]->dtype);
+        for (int j = 0; j <= k; ++j) {
+            const size_t bj = native_elems(ops[j], n_rhs[j]) * dtype_size(ops[j]->dtype);
+            if (ranges_overlap(b[k], bytes, x[j], bj) || (j < k && ranges_overlap(x[k], bytes, x[j], bj)))
+                return set_error(MRHS_EINVAL, "vectors of the batch overlap");
+        }
+    }
+    const size_t need = ws_bytes_sap_batched(ops, n_inst, n_rhs);
+    if (need && (!ws || ws_bytes < need)) return set_error(MRHS_EINVAL, "workspace too small");
+    return launch_sap_batched(ops, n_inst, b, x, n_rhs, n_sap, n_mr, ws, (hipStream_t)stream);
+}
+
 int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile)
 {
     if (int rc = check_op(op)) return rc;

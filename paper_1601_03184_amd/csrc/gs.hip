@@ -11,10 +11,10 @@
 // factorisations and triangular inverses of the n_tv x n_tv matrices run on the vector
 // units in LDS.
 //
-// MFMA lane layout (16x16x4): lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
-// D[4(l/16)+r][l%16] in accumulator register r.  A Gram matrix is a sum over rows, so the
-// accumulator of a 16-row transform (rows 4(l/16)+r) is used directly as the operand of
-// the next Gram product, with register r as the K step.
+// MFMA lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and holds D[l/16 + 4r][l%16] in accumulator register r.  A Gram matrix
+// is a sum over rows, so the accumulator of a 16-row transform (rows l/16 + 4r) is used
+// directly as the operand of the next Gram product, with register r as the K step.
 #include <climits>
 
 #include "internal.h"
@@ -178,7 +178,7 @@ template <int NT> __device__ inline void gram_store(const GramAcc &acc, Cplx *Gw
             const int p = pair_index(ti, tj);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = ti * 16 + 4 * (lane >> 4) + r, col = tj * 16 + (lane & 15);
+                const int row = ti * 16 + (lane >> 4) + 4 * r, col = tj * 16 + (lane & 15);
                 Gw[row * NP + col] = {acc.re[p][r], acc.im[p][r]};
             }
         }
@@ -297,7 +297,7 @@ template <int NT> __global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
         transform_block<NT>(a, i, h, b0, rows, G, NP, lane, dr, di);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int n = b0 + 4 * (lane >> 4) + r;
+            const int n = b0 + (lane >> 4) + 4 * r;
             if (n >= rows) continue;
             const size_t ro = row_offset(a, i, h, n);
 #pragma unroll

@@ -11,6 +11,8 @@
 //      and one LDS exchange, and the correction e kept in registers,
 //   3. writes x|_j (+)= e.
 // The links and clover of a site are loaded once per stencil for all T lanes of the site.
+#include <algorithm>
+
 #include "stencil.h"
 
 namespace {
@@ -85,20 +87,16 @@ __device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, c
     }
 }
 
+// One workgroup's share of a half-sweep: block blk, right-hand-side tile `tile`.
 template <typename Ts, typename Tc, int T>
-__global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
+__device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, unsigned char *smem)
 {
     using P2 = typename LdsPair<Tc>::type;
-    extern __shared__ __align__(16) unsigned char smem[];
     const KGeo &g = a.g;
     P2 *rho = reinterpret_cast<P2 *>(smem);
     const int str = g.Vb * T;
     Tc *red_s = reinterpret_cast<Tc *>(rho + 12 * str);  // [waves][T][3]
 
-    const int nwg = a.nblocks * a.ntiles;
-    const int li = xcd_remap(blockIdx.x, nwg);
-    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
-    const int blk = a.blocks[bi];
     const int off = threadIdx.x / T, t = threadIdx.x % T;
     const bool active = off < g.Vb;
     const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
@@ -216,6 +214,57 @@ __global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
     }
 }
 
+template <typename Ts, typename Tc, int T>
+__global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int li = xcd_remap(blockIdx.x, a.nblocks * a.ntiles);
+    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
+    sap_block<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
+}
+
+// Several operators (lattices of uneven size, each with its own right-hand sides) in one
+// launch per half-sweep: workgroup w (after the XCD remap) belongs to the instance whose
+// range [first[k], first[k+1]) holds it.  Descriptors travel by value in the kernel
+// arguments, so a captured graph replays without host memory.
+constexpr int MAX_BATCH = 8;
+
+template <typename Ts, typename Tc> struct SapBatch {
+    SapArgs<Ts, Tc> inst[MAX_BATCH];
+    int first[MAX_BATCH + 1];
+    int n_inst;
+};
+
+template <typename Ts, typename Tc, int T>
+__global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = xcd_remap(blockIdx.x, B.first[B.n_inst]);
+    int k = 0;
+    while (k + 1 < B.n_inst && w >= B.first[k + 1]) ++k;
+    const SapArgs<Ts, Tc> &a = B.inst[k];
+    const int li = w - B.first[k];
+    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
+    sap_block<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
+}
+
+struct CopyBatch {
+    const void *src[MAX_BATCH];
+    void *dst[MAX_BATCH];
+    long n[MAX_BATCH];  // elements
+    int n_inst;
+};
+
+template <typename Ts> __global__ void k_copy_batched(CopyBatch c)
+{
+    for (int k = 0; k < c.n_inst; ++k) {
+        const Ts *s = (const Ts *)c.src[k];
+        Ts *d = (Ts *)c.dst[k];
+        for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < c.n[k]; i += (long)gridDim.x * blockDim.x)
+            d[i] = s[i];
+    }
+}
+
 template <typename Ts> __global__ void k_fill_zero(Ts *__restrict__ p, long n)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = Ts(0);
@@ -302,7 +351,134 @@ int sap_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const voi
     return MRHS_OK;
 }
 
+template <typename Tc> const Tc *op_links(const mrhs_op *op);
+template <> const double *op_links<double>(const mrhs_op *op) { return op->links64; }
+template <> const float *op_links<float>(const mrhs_op *op) { return op->links32; }
+template <typename Tc> const Tc *op_clover(const mrhs_op *op);
+template <> const double *op_clover<double>(const mrhs_op *op) { return op->clover64; }
+template <> const float *op_clover<float>(const mrhs_op *op) { return op->clover32; }
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+template <typename Ts, typename Tc, int T>
+int launch_batched(const SapBatch<Ts, Tc> &B, int threads, size_t lds, hipStream_t st)
+{
+    static size_t done = 0;
+    if (lds > 65536 && lds > done) {
+        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_sap_batched<Ts, Tc, T>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                               "hipFuncSetAttribute(batched sap LDS)"))
+            return rc;
+        done = lds;
+    }
+    hipLaunchKernelGGL((k_sap_batched<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
+    return hip_check(hipGetLastError(), "k_sap_batched launch");
+}
+
+template <typename Ts, typename Tc>
+int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
+                         int n_sap, int n_mr, char *ws, hipStream_t st)
+{
+    // one tile for the whole batch: the smallest of the operators' tiles (all divide S)
+    int T = 4, maxVb = 0;
+    size_t max_lds = ops[0]->max_lds;
+    for (int k = 0; k < n; ++k) {
+        T = std::min(T, ops[k]->sap_tile);
+        maxVb = std::max(maxVb, ops[k]->k.Vb);
+    }
+    const int threads = round64(maxVb * T);
+    const size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + (size_t)(threads / 64) * T * 3);
+    if (maxVb * T > 1024 || lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "batched SAP tile does not fit");
+    if (n_sap == 0) {
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_fill_zero<Ts>, dim3(1024), dim3(256), 0, st, (Ts *)x[k], (long)native_elems(ops[k], n_rhs[k]));
+            if (int rc = hip_check(hipGetLastError(), "k_fill_zero launch")) return rc;
+        }
+        return MRHS_OK;
+    }
+    SapBatch<Ts, Tc> B{};
+    CopyBatch C{};
+    B.n_inst = n;
+    char *wp = ws;
+    Ts *snap[MAX_BATCH] = {};
+    for (int k = 0; k < n; ++k) {
+        const mrhs_op *op = ops[k];
+        SapArgs<Ts, Tc> &a = B.inst[k];
+        a.g = op->k;
+        a.links = op_links<Tc>(op);
+        a.clover = op_clover<Tc>(op);
+        a.blk_coords = op->blk_coords;
+        a.loc_coords = op->loc_coords;
+        a.ntiles = (n_rhs[k] + op->k.S - 1) / op->k.S * (op->k.S / T);
+        a.n_mr = n_mr;
+        a.b = (const Ts *)b[k];
+        a.x = (Ts *)x[k];
+        if (op->odd_blocks) {
+            snap[k] = (Ts *)wp;
+            wp += align256(native_elems(op, n_rhs[k]) * sizeof(Ts));
+        }
+    }
+    for (int s = 0; s < n_sap; ++s)
+        for (int c = 0; c < 2; ++c) {
+            C.n_inst = 0;
+            B.first[0] = 0;
+            for (int k = 0; k < n; ++k) {
+                const mrhs_op *op = ops[k];
+                SapArgs<Ts, Tc> &a = B.inst[k];
+                a.colour = c;
+                a.blocks = op->colour_blocks + (c == 0 ? 0 : op->n_colour[0]);
+                a.nblocks = op->n_colour[c];
+                a.mode = s == 0 ? c : 2;
+                a.xr = a.x;
+                if (a.mode == 2 && op->odd_blocks) {
+                    C.src[C.n_inst] = a.x;
+                    C.dst[C.n_inst] = snap[k];
+                    C.n[C.n_inst] = (long)native_elems(op, n_rhs[k]);
+                    ++C.n_inst;
+                    a.xr = snap[k];
+                }
+                B.first[k + 1] = B.first[k] + a.nblocks * a.ntiles;
+            }
+            if (C.n_inst) {
+                hipLaunchKernelGGL(k_copy_batched<Ts>, dim3(2048), dim3(256), 0, st, C);
+                if (int rc = hip_check(hipGetLastError(), "k_copy_batched launch")) return rc;
+            }
+            if (B.first[n] == 0) continue;
+            int rc;
+            switch (T) {
+            case 1: rc = launch_batched<Ts, Tc, 1>(B, threads, lds, st); break;
+            case 2: rc = launch_batched<Ts, Tc, 2>(B, threads, lds, st); break;
+            case 4: rc = launch_batched<Ts, Tc, 4>(B, threads, lds, st); break;
+            default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
+            }
+            if (rc) return rc;
+        }
+    return MRHS_OK;
+}
+
 }  // namespace
+
+size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs)
+{
+    size_t w = 0;
+    for (int k = 0; k < n; ++k)
+        if (ops[k]->odd_blocks) w += align256(native_elems(ops[k], n_rhs[k]) * dtype_size(ops[k]->dtype));
+    return w;
+}
+
+int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
+                       int n_sap, int n_mr, void *ws, hipStream_t st)
+{
+    if (n > MAX_BATCH) return set_error(MRHS_EUNSUPPORTED, "more than 8 operators in one batch");
+    switch (ops[0]->prec) {
+    case MRHS_PREC_F64:
+        return sap_batched_dispatch<double, double>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+    case MRHS_PREC_F32:
+        return sap_batched_dispatch<float, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+    default:
+        return sap_batched_dispatch<__half, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+    }
+}
 
 size_t ws_bytes_sap(const mrhs_op *op, int n_rhs)
 {

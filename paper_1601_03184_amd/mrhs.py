@@ -55,6 +55,8 @@ def lib():
             "block_orthonormalize": (i32, [p, p, i32, p, i32, i32, p, p, sz, p]),
             "coarse_op_build": (i32, [p, p, i32, i32, p, p, sz, p]),
             "mrhs_set_tiles": (i32, [p, i32, i32]),
+            "sap_smooth_mrhs_batched": (i32, [p, i32, p, p, p, i32, i32, p, sz, p]),
+            "mrhs_batched_workspace_bytes": (sz, [p, i32, p]),
             "mrhs_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -151,6 +153,30 @@ def block_orthonormalize(op, V, v_dtype, Q, q_dtype, n_tv, status, ws, stream=No
 def coarse_op_build(op, Q, q_dtype, n_tv, Dc, ws, stream=None):
     nb = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().coarse_op_build(op, _dptr(Q), int(q_dtype), int(n_tv), _dptr(Dc), _dptr(ws), nb, _stream(stream)))
+
+
+def _arrays(ops, bs, xs, n_rhs):
+    n = len(ops)
+    OA = (ctypes.c_void_p * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in ops])
+    NA = (ctypes.c_int32 * n)(*[int(k) for k in n_rhs])
+    BA = (ctypes.c_void_p * n)(*[t.data_ptr() for t in bs]) if bs is not None else None
+    XA = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs]) if xs is not None else None
+    return n, OA, NA, BA, XA
+
+
+def mrhs_batched_workspace_bytes(ops, n_rhs):
+    n, OA, NA, _, _ = _arrays(ops, None, None, n_rhs)
+    return lib().mrhs_batched_workspace_bytes(OA, n, NA)
+
+
+def sap_smooth_mrhs_batched(ops, bs, xs, n_rhs, n_sap, n_mr, ws, stream=None):
+    """ops: list of handles; bs, xs: lists of GPU native vectors; n_rhs: list of ints."""
+    for t in list(bs) + list(xs):
+        if not t.is_cuda:
+            raise ValueError("tensor must live on the GPU")
+    n, OA, NA, BA, XA = _arrays(ops, bs, xs, n_rhs)
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().sap_smooth_mrhs_batched(OA, n, BA, XA, NA, int(n_sap), int(n_mr), _dptr(ws), nb, _stream(stream)))
 
 
 def mrhs_set_tiles(op, sap_tile=0, dirac_tile=0):
