@@ -30,6 +30,7 @@ template <typename Tq> struct CoarseArgs {
     KGeo g;
     int a[4], na[4], astr[4];
     int Va, n_agg, N;
+    int agg0, nsl;  // this launch: aggregates agg0 .. agg0 + nsl - 1 (the workspace holds nsl)
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
@@ -48,9 +49,10 @@ __device__ inline void agg_local(const int (&a)[4], int ls, int (&lc)[4])
     }
 }
 
-// spinor of column (h', k') of P at native site ns: q_k' masked to spin half h'
-template <typename Tc, typename Tq>
-__device__ inline void load_pcol(const KGeo &g, const Tq *Q, int hp, int kp, int ns, Spinor<Tc> &s)
+// spinor of column (HP, k') of P at native site ns: q_k' masked to spin half HP (the half
+// is a template parameter so that the masked spinor stays in registers)
+template <int HP, typename Tc, typename Tq>
+__device__ inline void load_pcol(const KGeo &g, const Tq *Q, int kp, int ns, Spinor<Tc> &s)
 {
     const int blk = ns / g.Vb, off = ns - blk * g.Vb;
     const int grp = kp / g.S, t = kp - grp * g.S;
@@ -58,7 +60,7 @@ __device__ inline void load_pcol(const KGeo &g, const Tq *Q, int hp, int kp, int
     const size_t cs = (size_t)g.Vb * g.S;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        if (c / 6 == hp) {
+        if (c / 6 == HP) {
             s.re[c] = (Tc)Q[base + (2 * c) * cs];
             s.im[c] = (Tc)Q[base + (2 * c + 1) * cs];
         } else {
@@ -67,14 +69,14 @@ __device__ inline void load_pcol(const KGeo &g, const Tq *Q, int hp, int kp, int
     }
 }
 
-template <int MU, typename Tc, typename Tq>
+template <int MU, int HP, typename Tc, typename Tq>
 __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int i, int ls, int ns, const int (&lc)[4],
-                                   int hp, int kp, Spinor<Tc> &w)
+                                   int kp, Spinor<Tc> &w)
 {
     if (lc[MU] + 1 < a.a[MU]) {
         const int nn = a.agg_sites[(size_t)i * a.Va + ls + a.astr[MU]];
         Spinor<Tc> chi;
-        load_pcol<Tc>(a.g, a.Q, hp, kp, nn, chi);
+        load_pcol<HP, Tc>(a.g, a.Q, kp, nn, chi);
         Tc U[18];
         load_link(links, a.g.V, MU, ns, U);
         hop_accumulate<MU, -1, false>(U, chi, w);
@@ -83,7 +85,7 @@ __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int
     if (lc[MU] > 0) {
         const int nn = a.agg_sites[(size_t)i * a.Va + ls - a.astr[MU]];
         Spinor<Tc> chi;
-        load_pcol<Tc>(a.g, a.Q, hp, kp, nn, chi);
+        load_pcol<HP, Tc>(a.g, a.Q, kp, nn, chi);
         Tc U[18];
         load_link(links, a.g.V, MU, nn, U);
         hop_accumulate<MU, +1, true>(U, chi, w);
@@ -91,12 +93,12 @@ __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int
     hop_fence(w);
 }
 
-// workspace element of column (h', k' = grp*S + t), aggregate i, real component r, site sidx
-// of a set of nsites sites per aggregate
+// workspace element of column (h', k' = grp*S + t), aggregate i (of this launch's slice),
+// real component r, site sidx of a set of nsites sites per aggregate
 template <typename Tq>
 __device__ inline size_t wcol_index(const CoarseArgs<Tq> &a, int hp, int grp, int i, int r, int nsites, int sidx, int t)
 {
-    return (((((size_t)hp * a.ngrp + grp) * a.n_agg + i) * 24 + r) * nsites + sidx) * a.g.S + t;
+    return (((((size_t)hp * a.ngrp + grp) * a.nsl + (i - a.agg0)) * 24 + r) * nsites + sidx) * a.g.S + t;
 }
 
 // local site of the f-th site on the +mu face of an aggregate (local coordinate mu = a_mu - 1)
@@ -106,9 +108,9 @@ __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu,
     return f % st + st * (a[mu] - 1) + st * a[mu] * (f / st);
 }
 
-template <int MU, typename Tc, typename Tq>
-__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int hp, int kp, int i,
-                                   int grp, int t)
+template <int MU, int HP, typename Tc, typename Tq>
+__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int kp, int i, int grp,
+                                   int t)
 {
     const KGeo &g = a.g;
     const int blk = ns / g.Vb, off = ns - blk * g.Vb;
@@ -116,7 +118,7 @@ __device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int
     decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lcb);
     const NbrSite n = nbr_fwd(g, MU, blk, off, bc, lcb);
     Spinor<Tc> chi, w;
-    load_pcol<Tc>(g, a.Q, hp, kp, n.blk * g.Vb + n.off, chi);
+    load_pcol<HP, Tc>(g, a.Q, kp, n.blk * g.Vb + n.off, chi);
     Tc U[18];
     load_link(links, g.V, MU, ns, U);
     spinor_zero(w);
@@ -128,8 +130,8 @@ __device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int
     float *dst = a.Wf[MU];
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
-        dst[wcol_index(a, hp, grp, i, 2 * q, nf, f, t)] = (float)w.re[q];
-        dst[wcol_index(a, hp, grp, i, 2 * q + 1, nf, f, t)] = (float)w.im[q];
+        dst[wcol_index(a, HP, grp, i, 2 * q, nf, f, t)] = (float)w.re[q];
+        dst[wcol_index(a, HP, grp, i, 2 * q + 1, nf, f, t)] = (float)w.im[q];
     }
 }
 
@@ -137,12 +139,10 @@ __device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int
 // The S lanes of a site read the S test vectors of a group from one contiguous run.
 template <typename Tc> constexpr int cols_threads() { return sizeof(Tc) == 8 ? 512 : 1024; }
 
-template <typename Tc, typename Tq>
-__global__ void __launch_bounds__(cols_threads<Tc>()) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
-                                                      const Tc *__restrict__ clover)
+template <int HP, typename Tc, typename Tq>
+__device__ inline void coarse_cols_half(const CoarseArgs<Tq> &a, const Tc *__restrict__ links,
+                                        const Tc *__restrict__ clover, int i, int grp)
 {
-    const int i = blockIdx.x;
-    const int hp = blockIdx.y / a.ngrp, grp = blockIdx.y - hp * a.ngrp;
     const int S = a.g.S;
     for (int e = threadIdx.x; e < a.Va * S; e += blockDim.x) {
         const int ls = e / S, t = e - ls * S;
@@ -152,28 +152,44 @@ __global__ void __launch_bounds__(cols_threads<Tc>()) k_coarse_cols(CoarseArgs<T
         agg_local(a.a, ls, lc);
         {
             Spinor<Tc> p, w;
-            load_pcol<Tc>(a.g, a.Q, hp, kp, ns, p);
-            clover_site(clover, a.g.V, ns, p, w);
+            load_pcol<HP, Tc>(a.g, a.Q, kp, ns, p);
+            // the site term is block-diagonal in the spin halves: only half HP is non-zero
+            spinor_zero(w);
+            {
+                Tc A[36];
+                load_clover_half<HP>(clover, a.g.V, ns, A);
+                clover_half<HP>(A, p, w);
+            }
             hop_fence(w);
-            inside_hops<0>(a, links, i, ls, ns, lc, hp, kp, w);
-            inside_hops<1>(a, links, i, ls, ns, lc, hp, kp, w);
-            inside_hops<2>(a, links, i, ls, ns, lc, hp, kp, w);
-            inside_hops<3>(a, links, i, ls, ns, lc, hp, kp, w);
+            inside_hops<0, HP>(a, links, i, ls, ns, lc, kp, w);
+            inside_hops<1, HP>(a, links, i, ls, ns, lc, kp, w);
+            inside_hops<2, HP>(a, links, i, ls, ns, lc, kp, w);
+            inside_hops<3, HP>(a, links, i, ls, ns, lc, kp, w);
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
-                a.W0[wcol_index(a, hp, grp, i, 2 * q, a.Va, ls, t)] = (float)w.re[q];
-                a.W0[wcol_index(a, hp, grp, i, 2 * q + 1, a.Va, ls, t)] = (float)w.im[q];
+                a.W0[wcol_index(a, HP, grp, i, 2 * q, a.Va, ls, t)] = (float)w.re[q];
+                a.W0[wcol_index(a, HP, grp, i, 2 * q + 1, a.Va, ls, t)] = (float)w.im[q];
             }
         }
         sched_fence();
-        if (lc[0] == a.a[0] - 1) face_column<0>(a, links, ns, ls, hp, kp, i, grp, t);
+        if (lc[0] == a.a[0] - 1) face_column<0, HP>(a, links, ns, ls, kp, i, grp, t);
         sched_fence();
-        if (lc[1] == a.a[1] - 1) face_column<1>(a, links, ns, ls, hp, kp, i, grp, t);
+        if (lc[1] == a.a[1] - 1) face_column<1, HP>(a, links, ns, ls, kp, i, grp, t);
         sched_fence();
-        if (lc[2] == a.a[2] - 1) face_column<2>(a, links, ns, ls, hp, kp, i, grp, t);
+        if (lc[2] == a.a[2] - 1) face_column<2, HP>(a, links, ns, ls, kp, i, grp, t);
         sched_fence();
-        if (lc[3] == a.a[3] - 1) face_column<3>(a, links, ns, ls, hp, kp, i, grp, t);
+        if (lc[3] == a.a[3] - 1) face_column<3, HP>(a, links, ns, ls, kp, i, grp, t);
     }
+}
+
+template <typename Tc, typename Tq>
+__global__ void __launch_bounds__(cols_threads<Tc>()) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
+                                                                      const Tc *__restrict__ clover)
+{
+    const int i = a.agg0 + blockIdx.x;
+    const int hp = blockIdx.y / a.ngrp, grp = blockIdx.y - hp * a.ngrp;
+    if (hp == 0) coarse_cols_half<0>(a, links, clover, i, grp);
+    else coarse_cols_half<1>(a, links, clover, i, grp);
 }
 
 // grid: (aggregate i, block d = 0 self, 1..4 = +mu).  The 2N x 2N block is a sum over the
@@ -194,7 +210,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
     const int N = a.N, N2 = 2 * N;
     float2 *Qs = reinterpret_cast<float2 *>(smem);  // [CHS][12][N]
     float2 *Ws = Qs + CHS * 12 * N;                // [CHS][12][2N]
-    const int i = blockIdx.x, d = blockIdx.y;
+    const int i = a.agg0 + blockIdx.x, d = blockIdx.y;
     const int mu = d - 1;
     const int nsites = d == 0 ? a.Va : a.Va / a.a[mu];
     const float *Wsrc = d == 0 ? a.W0 : a.Wf[mu];
@@ -297,9 +313,26 @@ template <typename Tq> __global__ void k_coarse_back(CoarseArgs<Tq> a)
     }
 }
 
+// workspace columns of one aggregate: the self columns on all its sites and the face
+// columns on its four forward faces
+size_t coarse_bytes_per_agg(const mrhs_op *op, int n_tv)
+{
+    size_t sites = op->Va;
+    for (int mu = 0; mu < 4; ++mu) sites += op->Va / op->g.agg[mu];
+    const size_t cols = (size_t)2 * ((n_tv + op->k.S - 1) / op->k.S) * op->k.S;
+    return sizeof(float) * cols * sites * 24;
+}
+
+// aggregates per launch: as many as fit ws_bytes of workspace (the caller guarantees one)
+int coarse_slice(const mrhs_op *op, int n_tv, size_t ws_bytes)
+{
+    const size_t n = std::max((size_t)1, ws_bytes / coarse_bytes_per_agg(op, n_tv));
+    return (int)std::min(n, (size_t)op->n_agg);
+}
+
 template <typename Tc, typename Tq>
 int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc, void *ws,
-                    hipStream_t st)
+                    size_t ws_bytes, hipStream_t st)
 {
     CoarseArgs<Tq> a{};
     a.g = op->k;
@@ -322,43 +355,52 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.W0 = (float *)ws;
     {
         const size_t cols = (size_t)2 * a.ngrp * op->k.S;  // padded columns
-        float *p = a.W0 + cols * op->n_agg * op->Va * 24;
+        const size_t sl = coarse_slice(op, n_tv, ws_bytes);
+        float *p = a.W0 + cols * sl * op->Va * 24;
         for (int mu = 0; mu < 4; ++mu) {
             a.Wf[mu] = p;
-            p += cols * op->n_agg * (op->Va / op->g.agg[mu]) * 24;
+            p += cols * sl * (op->Va / op->g.agg[mu]) * 24;
         }
     }
     if (!a.Q || !a.Dc || !a.W0 || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
     const int cthreads = std::min(cols_threads<Tc>(), (op->Va * op->k.S + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(op->n_agg, 2 * a.ngrp), dim3(cthreads), 0, st, a, links, clover);
-    if (int rc = hip_check(hipGetLastError(), "k_coarse_cols launch")) return rc;
     const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
-    hipLaunchKernelGGL((k_coarse_blocks<Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a);
-    if (int rc = hip_check(hipGetLastError(), "k_coarse_blocks launch")) return rc;
+    const int slice = coarse_slice(op, n_tv, ws_bytes);
+    for (int agg0 = 0; agg0 < op->n_agg; agg0 += slice) {
+        a.agg0 = agg0;
+        a.nsl = std::min(slice, op->n_agg - agg0);
+        hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(a.nsl, 2 * a.ngrp), dim3(cthreads), 0, st, a, links, clover);
+        if (int rc = hip_check(hipGetLastError(), "k_coarse_cols launch")) return rc;
+        hipLaunchKernelGGL((k_coarse_blocks<Tq>), dim3(a.nsl, 5), dim3(NTHR), lds, st, a);
+        if (int rc = hip_check(hipGetLastError(), "k_coarse_blocks launch")) return rc;
+    }
     hipLaunchKernelGGL((k_coarse_back<Tq>), dim3(op->n_agg, 4), dim3(NTHR), 0, st, a);
     return hip_check(hipGetLastError(), "k_coarse_back launch");
 }
 
 }  // namespace
 
+// the workspace asked for: all aggregates in one launch pair, capped at 1 GiB
 size_t ws_bytes_coarse(const mrhs_op *op, int n_tv)
 {
-    size_t sites = op->Va;
-    for (int mu = 0; mu < 4; ++mu) sites += op->Va / op->g.agg[mu];
-    const size_t cols = (size_t)2 * ((n_tv + op->k.S - 1) / op->k.S) * op->k.S;
-    return sizeof(float) * cols * op->n_agg * sites * 24;
+    const size_t per = coarse_bytes_per_agg(op, n_tv);
+    return std::max(per, std::min((size_t)op->n_agg * per, (size_t)1 << 30) / per * per);
 }
 
-int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, hipStream_t st)
+// the least workspace that works: one aggregate per launch pair
+size_t ws_bytes_coarse_min(const mrhs_op *op, int n_tv) { return coarse_bytes_per_agg(op, n_tv); }
+
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, size_t ws_bytes,
+                  hipStream_t st)
 {
     if (2 * n_tv * 2 * n_tv > 16 * NTHR) return set_error(MRHS_EUNSUPPORTED, "more than 32 test vectors");
     if (op->links32) {
         if (qdt == MRHS_DTYPE_F32)
-            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, ws, st);
-        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, ws, st);
+            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, ws, ws_bytes, st);
+        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, ws, ws_bytes, st);
     }
     if (qdt == MRHS_DTYPE_F32)
-        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, ws, st);
-    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, ws, st);
+        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, ws, ws_bytes, st);
+    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, ws, ws_bytes, st);
 }

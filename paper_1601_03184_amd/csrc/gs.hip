@@ -7,14 +7,19 @@
 //   G1 = V^dag V = R1^dag R1,  Q1 = V R1^-1,  G2 = Q1^dag Q1 = R2^dag R2,  Q = V (R1^-1 R2^-1),
 // the thin QR factor with a real positive triangular diagonal (the Q that Gram-Schmidt
 // with re-orthogonalisation produces).  The products V^dag V, V M and Q1^dag Q1 run on
-// v_mfma_f64_16x16x4f64 (16x16 output tiles, complex = 4 real products); the Cholesky
-// factorisations and triangular inverses of the n_tv x n_tv matrices run on the vector
-// units in LDS.
+// v_mfma_f64_16x16x4f64 (16x16 output tiles, complex = 4 real products, only the upper
+// tiles of a Hermitian product, only the non-zero K steps of a triangular one); the
+// Cholesky factorisations and triangular inverses of the n_tv x n_tv matrices run on the
+// vector units in LDS and registers.
+//
+// V is read three times, in 16-row blocks that each wavefront loads one block ahead of the
+// one on the matrix cores; the row offsets of the aggregate's sites are staged in LDS.  Q1
+// is never stored: each 16-row block of it passes through the wavefront's own LDS rows
+// into the second Gram product.
 //
 // MFMA lane layout of v_mfma_f64_16x16x4f64 (measured on gfx950): lane l supplies A[l%16][l/16]
-// and B[l/16][l%16] and holds D[l/16 + 4r][l%16] in accumulator register r.  A Gram matrix
-// is a sum over rows, so the accumulator of a 16-row transform (rows l/16 + 4r) is used
-// directly as the operand of the next Gram product, with register r as the K step.
+// and B[l/16][l%16] and holds D[l/16 + 4r][l%16] in accumulator register r.
+#include <algorithm>
 #include <climits>
 
 #include "internal.h"
@@ -24,15 +29,14 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NTHR = 256;  // 4 wavefronts
 constexpr int NW = NTHR / 64;
+constexpr int SCH = 1024;  // aggregate sites whose row offsets are staged in LDS at a time
 
 struct GsArgs {
     KGeo g;
-    int Va, n_tv, NT;  // NT = NP / 16 column tiles
+    int Va, n_tv;
     const int32_t *agg_sites;
     const void *V;
-    int vdt;
     void *Q;
-    int qdt;
     int32_t *status;
 };
 
@@ -40,38 +44,19 @@ struct Cplx {
     double re, im;
 };
 
-__device__ inline double load_elem(const void *p, int dt, size_t i)
-{
-    if (dt == MRHS_DTYPE_F64) return ((const double *)p)[i];
-    if (dt == MRHS_DTYPE_F32) return (double)((const float *)p)[i];
-    return (double)__half2float(((const __half *)p)[i]);
-}
-
-__device__ inline void store_elem(void *p, int dt, size_t i, double v)
-{
-    if (dt == MRHS_DTYPE_F64) ((double *)p)[i] = v;
-    else ((float *)p)[i] = (float)v;
-}
-
-// native element offset of row n of half h of aggregate i (column part excluded), real part
-__device__ inline size_t row_offset(const GsArgs &a, int i, int h, int n)
-{
-    const KGeo &g = a.g;
-    const int ls = n / 6, sp = (n % 6) / 3, c = n % 3;
-    const int ns = a.agg_sites[(size_t)i * a.Va + ls];
-    const int blk = ns / g.Vb, off = ns - blk * g.Vb;
-    const int r = 2 * (3 * (2 * h + sp) + c);
-    return (((size_t)blk * 24 + r) * g.Vb + off) * g.S;
-}
-
-// native element offset of column k (test vector), row part excluded
-__device__ inline size_t col_offset(const GsArgs &a, int k)
-{
-    const int grp = k / a.g.S, t = k - grp * a.g.S;
-    return (size_t)grp * a.g.nblk * 24 * a.g.Vb * a.g.S + t;
-}
+template <typename T> __device__ inline double to_f64(T v) { return (double)v; }
+template <> __device__ inline double to_f64<__half>(__half v) { return (double)__half2float(v); }
 
 __device__ inline d4 mfma(double x, double y, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0); }
+
+// Row n of V^h_i (local site n / 6, spin in the half, colour) inside the staged range of
+// sites: native element offset without the column part.
+__device__ inline uint32_t row_off(const uint32_t *sbase, int h, uint32_t cstr, int n)
+{
+    const int sl = n / 6, q = n - 6 * sl;
+    const int sp = q >= 3 ? 1 : 0, c = q - 3 * sp;
+    return sbase[sl] + (uint32_t)(2 * (3 * (2 * h + sp) + c)) * cstr;
+}
 
 // G (NP x NP, upper triangle, in place) -> R with G = R^dag R.  Flags a pivot that falls to
 // <= 1e-14 of the column's original squared norm, i.e. T_kk <= 1e-7 ||v_k||: the Gram
@@ -109,23 +94,47 @@ __device__ void cholesky_inplace(Cplx *G, const double *diag0, int N, int NP, in
     __syncthreads();
 }
 
-// X = R^-1 for upper-triangular R (NP x NP in LDS); one thread per column.
-__device__ void tri_inverse(const Cplx *R, Cplx *X, int NP)
+// X = R^-1 for upper-triangular R (NP x NP in LDS).  Column l is solved by 8 lanes of one
+// wavefront, bottom row first: X[k][l] = (delta_kl - sum_{k<j<=l} R[k][j] X[j][l]) / R[k][k];
+// lane `sub` keeps rows j = sub (mod 8) of the column in registers, the partial sums are
+// combined with shuffles.
+template <int NP> __device__ void tri_inverse(const Cplx *R, Cplx *X)
 {
-    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) X[e] = {0.0, 0.0};
-    __syncthreads();
-    for (int l = threadIdx.x; l < NP; l += blockDim.x) {
-        X[l * NP + l] = {1.0 / R[l * NP + l].re, 0.0};
-        for (int k = l - 1; k >= 0; --k) {
-            double sr = 0, si = 0;
-            for (int j = k + 1; j <= l; ++j) {
-                const Cplx r = R[k * NP + j], x = X[j * NP + l];
-                sr += r.re * x.re - r.im * x.im;
-                si += r.re * x.im + r.im * x.re;
+    constexpr int NJ = NP / 8;
+    const int l = threadIdx.x >> 3, sub = threadIdx.x & 7;
+    const bool col = l < NP;
+    double xr[NJ], xi[NJ];
+#pragma unroll
+    for (int m = 0; m < NJ; ++m) xr[m] = xi[m] = 0.0;
+#pragma unroll
+    for (int k = NP - 1; k >= 0; --k) {
+        double sr = 0.0, si = 0.0;
+        if (col) {
+#pragma unroll
+            for (int m = 0; m < NJ; ++m) {
+                const int j = sub + 8 * m;
+                if (j > k && j <= l) {
+                    const Cplx r = R[k * NP + j];
+                    sr += r.re * xr[m] - r.im * xi[m];
+                    si += r.re * xi[m] + r.im * xr[m];
+                }
             }
-            const double d = R[k * NP + k].re;
-            X[k * NP + l] = {-sr / d, -si / d};
         }
+        sr += __shfl_xor(sr, 1, 64);
+        si += __shfl_xor(si, 1, 64);
+        sr += __shfl_xor(sr, 2, 64);
+        si += __shfl_xor(si, 2, 64);
+        sr += __shfl_xor(sr, 4, 64);
+        si += __shfl_xor(si, 4, 64);
+        if (col && k <= l && sub == (k & 7)) {
+            const double d = R[k * NP + k].re;
+            xr[k >> 3] = (k == l ? 1.0 : -sr) / d;
+            xi[k >> 3] = (k == l ? 0.0 : -si) / d;
+        }
+    }
+    if (col) {
+#pragma unroll
+        for (int m = 0; m < NJ; ++m) X[(sub + 8 * m) * NP + l] = {xr[m], xi[m]};
     }
     __syncthreads();
 }
@@ -168,8 +177,8 @@ template <int NT> __device__ inline void gram_step(const double (&xr)[2], const 
         }
 }
 
-// write this wavefront's Gram tiles (upper triangle of tiles) to Gw (NP x NP complex)
-template <int NT> __device__ inline void gram_store(const GramAcc &acc, Cplx *Gw, int NP, int lane)
+// add (or, for the first wavefront, write) this wavefront's Gram tiles into G
+template <int NT> __device__ inline void gram_accumulate(const GramAcc &acc, Cplx *G, int NP, int lane, bool first)
 {
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
@@ -179,32 +188,101 @@ template <int NT> __device__ inline void gram_store(const GramAcc &acc, Cplx *Gw
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = ti * 16 + (lane >> 4) + 4 * r, col = tj * 16 + (lane & 15);
-                Gw[row * NP + col] = {acc.re[p][r], acc.im[p][r]};
+                Cplx v = {acc.re[p][r], acc.im[p][r]};
+                if (!first) {
+                    v.re += G[row * NP + col].re;
+                    v.im += G[row * NP + col].im;
+                }
+                G[row * NP + col] = v;
             }
         }
 }
 
-// 16-row block transform: tile tj of (rows b0..b0+15 of V) M for upper-triangular M
-// (NP x NP in LDS).  Lane l supplies V[b0 + l%16][4 ks + l/16] and M[4 ks + l/16][16 tj + l%16].
-template <int NT>
-__device__ inline void transform_block(const GsArgs &a, int i, int h, int b0, int rows, const Cplx *M, int NP, int lane,
-                                       d4 (&dr)[2], d4 (&di)[2])
+// the wavefronts' partial Gram matrices summed into G in a fixed order
+template <int NT> __device__ inline void gram_reduce(const GramAcc &acc, Cplx *G, int NP, int lane, int wave)
 {
-    const int N = a.n_tv;
-    const int rr = b0 + (lane & 15);
-    const size_t cstr = (size_t)a.g.Vb * a.g.S;
-    const size_t ro = rr < rows ? row_offset(a, i, h, rr) : 0;
+    for (int w = 0; w < NW; ++w) {
+        if (wave == w) gram_accumulate<NT>(acc, G, NP, lane, w == 0);
+        __syncthreads();
+    }
+}
+
+// Operands of one 16-row block for a Gram product: K step j covers rows b0 + 4j .. b0 + 4j + 3;
+// lane l holds row b0 + 4j + l/16 of columns 16 t + l%16.
+template <typename Tv, int NT> struct GramRaw {
+    Tv v[4][NT][2];
+};
+
+template <typename Tv, int NT>
+__device__ inline void load_gram(const Tv *V, const uint32_t *sbase, const size_t *coff, int h, uint32_t cstr, int b0,
+                                 int nrows, int N, int lane, GramRaw<Tv, NT> &o)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int n = b0 + 4 * j + (lane >> 4);
+        const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            // out-of-range operands read element 0 and are replaced by zero
+            const int k = 16 * t + (lane & 15);
+            const bool ok = n < nrows && k < N;
+            const size_t idx = ok ? ro + coff[k] : 0;
+            const Tv re = V[idx], im = V[ok ? idx + cstr : 0];
+            o.v[j][t][0] = ok ? re : Tv(0);
+            o.v[j][t][1] = ok ? im : Tv(0);
+        }
+    }
+}
+
+template <typename Tv, int NT> __device__ inline void gram_block(const GramRaw<Tv, NT> &o, GramAcc &acc)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            xr[t] = to_f64(o.v[j][t][0]);
+            xi[t] = to_f64(o.v[j][t][1]);
+        }
+        gram_step<NT>(xr, xi, acc);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Operands of one 16-row block for a transform V M: lane l holds row b0 + l%16 of columns
+// 4 ks + l/16.
+template <typename Tv, int NT> struct TransRaw {
+    Tv v[4 * NT][2];
+};
+
+template <typename Tv, int NT>
+__device__ inline void load_trans(const Tv *V, const uint32_t *sbase, const size_t *coff, int h, uint32_t cstr, int b0,
+                                  int nrows, int N, int lane, TransRaw<Tv, NT> &o)
+{
+    const int n = b0 + (lane & 15);
+    const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
+#pragma unroll
+    for (int ks = 0; ks < 4 * NT; ++ks) {
+        const int k = 4 * ks + (lane >> 4);
+        const bool ok = n < nrows && k < N;
+        const size_t idx = ok ? ro + coff[k] : 0;
+        const Tv re = V[idx], im = V[ok ? idx + cstr : 0];
+        o.v[ks][0] = ok ? re : Tv(0);
+        o.v[ks][1] = ok ? im : Tv(0);
+    }
+}
+
+// tile tj of (the 16 rows) M for upper-triangular M (NP x NP in LDS); the accumulator of
+// tile tj holds rows b0 + l/16 + 4r of columns 16 tj + l%16 in register r
+template <typename Tv, int NT>
+__device__ inline void trans_block(const TransRaw<Tv, NT> &o, const Cplx *M, int NP, int lane, d4 (&dr)[2], d4 (&di)[2])
+{
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) dr[tj] = di[tj] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < NT * 4; ++ks) {
-        const int k = ks * 4 + (lane >> 4);  // column of V = row of M
-        double vr = 0.0, vi = 0.0;
-        if (rr < rows && k < N) {
-            const size_t idx = ro + col_offset(a, k);
-            vr = load_elem(a.V, a.vdt, idx);
-            vi = load_elem(a.V, a.vdt, idx + cstr);
-        }
+        const int k = 4 * ks + (lane >> 4);  // column of V = row of M
+        const double vr = to_f64(o.v[ks][0]), vi = to_f64(o.v[ks][1]);
 #pragma unroll
         for (int tj = 0; tj < NT; ++tj) {
             if (ks * 4 >= (tj + 1) * 16) continue;  // M is upper triangular
@@ -214,100 +292,155 @@ __device__ inline void transform_block(const GsArgs &a, int i, int h, int b0, in
             di[tj] = mfma(vr, m.im, di[tj]);
             di[tj] = mfma(vi, m.re, di[tj]);
         }
+        // one K step at a time: keeps the converted operands of later steps out of registers
+        __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <int NT> __global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
+// native offsets of the staged aggregate sites [ls0, ls0 + n): block and site part
+__device__ inline void stage_sites(const GsArgs &a, int i, int ls0, int n, uint32_t *sbase)
+{
+    const KGeo &g = a.g;
+    __syncthreads();
+    for (int s = threadIdx.x; s < n; s += blockDim.x) {
+        const int ns = a.agg_sites[(size_t)i * a.Va + ls0 + s];
+        const int blk = ns / g.Vb, off = ns - blk * g.Vb;
+        sbase[s] = ((uint32_t)blk * 24u * (uint32_t)g.Vb + (uint32_t)off) * (uint32_t)g.S;
+    }
+    __syncthreads();
+}
+
+// One workgroup per (aggregate i, half h).  Every pass walks the rows in 16-row blocks,
+// NW blocks apart per wavefront, with the next block's elements loaded while the current
+// one is on the matrix cores.
+template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;
     const int N = a.n_tv;
-    Cplx *Gp = reinterpret_cast<Cplx *>(smem);  // [NW][NP*NP] partial Gram matrices
-    Cplx *G = Gp + NW * NP * NP;                // reduced Gram matrix / Cholesky factor / M
-    Cplx *X1 = G + NP * NP;                     // R1^-1
-    Cplx *X2 = X1 + NP * NP;                    // R2^-1
-    double *diag0 = reinterpret_cast<double *>(X2 + NP * NP);
+    constexpr int UNION = 2 * NP * NP > 64 * NP ? 2 * NP * NP : 64 * NP;
+    Cplx *X1 = reinterpret_cast<Cplx *>(smem);  // R1^-1
+    Cplx *G = X1 + NP * NP;                      // Gram matrix / Cholesky factor / R1^-1 R2^-1
+    Cplx *X2 = G + NP * NP;                      // R2^-1
+    Cplx *Qw = G;  // during the second Gram pass: 16 rows of Q1 per wavefront (over G and X2)
+    double *diag0 = reinterpret_cast<double *>(G + UNION);
+    size_t *coff = reinterpret_cast<size_t *>(diag0 + NP);
+    uint32_t *sbase = reinterpret_cast<uint32_t *>(coff + NP);
     __shared__ int bad;
 
+    const Tv *V = static_cast<const Tv *>(a.V);
+    Tq *Q = static_cast<Tq *>(a.Q);
     const int i = blockIdx.x >> 1, h = blockIdx.x & 1;
-    const int rows = 6 * a.Va;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const size_t cstr = (size_t)a.g.Vb * a.g.S;
+    const uint32_t cstr = (uint32_t)a.g.Vb * (uint32_t)a.g.S;
+    const size_t gstr = (size_t)a.g.nblk * 24 * cstr;  // one group of S test vectors
     if (threadIdx.x == 0) bad = 0;
+    for (int k = threadIdx.x; k < NP; k += blockDim.x) coff[k] = (size_t)(k / a.g.S) * gstr + (k % a.g.S);
+    int staged = -1;  // first site of the staged range
 
-    for (int pass = 0; pass < 2; ++pass) {
-        GramAcc acc;
+    // G1 = V^dag V
+    GramAcc acc;
 #pragma unroll
-        for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
-        if (pass == 0) {
-            // G1 = V^dag V: K steps of 4 rows, spread over the wavefronts
-            size_t co[2] = {0, 0};
+    for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
+        const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
+        if (staged != ls0) {
+            stage_sites(a, i, ls0, nsc, sbase);
+            staged = ls0;
+        }
+        int b0 = wave * 16;
+        GramRaw<Tv, NT> cur, nxt;
+        if (b0 < nrows) load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
+        for (; b0 < nrows; b0 += NW * 16) {
+            if (b0 + NW * 16 < nrows) load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
+            gram_block<Tv, NT>(cur, acc);
+            cur = nxt;
+        }
+    }
+    __syncthreads();
+    gram_reduce<NT>(acc, G, NP, lane, wave);
+    for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = G[k * NP + k].re;
+    cholesky_inplace(G, diag0, N, NP, &bad);
+    tri_inverse<NP>(G, X1);
+
+    // G2 = Q1^dag Q1 with Q1 = V R1^-1 formed block by block on the matrix cores
 #pragma unroll
-            for (int t = 0; t < NT; ++t) co[t] = col_offset(a, t * 16 + (lane & 15));
-            const int nsteps = (rows + 3) / 4;
-            for (int s = wave; s < nsteps; s += NW) {
-                const int n = s * 4 + (lane >> 4);
+    for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
+        const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
+        if (staged != ls0) {
+            stage_sites(a, i, ls0, nsc, sbase);
+            staged = ls0;
+        }
+        int b0 = wave * 16;
+        TransRaw<Tv, NT> cur, nxt;
+        if (b0 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
+        for (; b0 < nrows; b0 += NW * 16) {
+            if (b0 + NW * 16 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
+            d4 dr[2], di[2];
+            trans_block<Tv, NT>(cur, X1, NP, lane, dr, di);
+            // the 16 rows of Q1 go through this wavefront's LDS rows, from which the Gram
+            // product reads them in its own operand layout
+            Cplx *qw = Qw + wave * 16 * NP;
+#pragma unroll
+            for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    qw[((lane >> 4) + 4 * r) * NP + 16 * tj + (lane & 15)] = {dr[tj][r], di[tj][r]};
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
                 double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
-                if (n < rows) {
-                    const size_t ro = row_offset(a, i, h, n);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        if (t * 16 + (lane & 15) < N) {
-                            xr[t] = load_elem(a.V, a.vdt, ro + co[t]);
-                            xi[t] = load_elem(a.V, a.vdt, ro + co[t] + cstr);
-                        }
+                for (int t = 0; t < NT; ++t) {
+                    const Cplx q = qw[(4 * j + (lane >> 4)) * NP + 16 * t + (lane & 15)];
+                    xr[t] = q.re;
+                    xi[t] = q.im;
                 }
                 gram_step<NT>(xr, xi, acc);
+                __builtin_amdgcn_sched_barrier(0);
             }
-        } else {
-            // G2 = Q1^dag Q1, Q1 = V R1^-1 formed 16 rows at a time on the matrix cores
-            for (int b0 = wave * 16; b0 < rows; b0 += NW * 16) {
-                d4 dr[2], di[2];
-                transform_block<NT>(a, i, h, b0, rows, X1, NP, lane, dr, di);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            cur = nxt;
+        }
+    }
+    __syncthreads();
+    gram_reduce<NT>(acc, G, NP, lane, wave);
+    for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = 1.0;
+    cholesky_inplace(G, diag0, N, NP, &bad);
+    tri_inverse<NP>(G, X2);
+    tri_product(X1, X2, G, NP);  // G <- R1^-1 R2^-1
+    // Q = V (R1^-1 R2^-1)
+    for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
+        const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
+        if (staged != ls0) {
+            stage_sites(a, i, ls0, nsc, sbase);
+            staged = ls0;
+        }
+        int b0 = wave * 16;
+        TransRaw<Tv, NT> cur, nxt;
+        if (b0 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
+        for (; b0 < nrows; b0 += NW * 16) {
+            if (b0 + NW * 16 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
+            d4 dr[2], di[2];
+            trans_block<Tv, NT>(cur, G, NP, lane, dr, di);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const double xr[2] = {dr[0][r], dr[1][r]};
-                    const double xi[2] = {di[0][r], di[1][r]};
-                    gram_step<NT>(xr, xi, acc);
+            for (int r = 0; r < 4; ++r) {
+                const int n = b0 + (lane >> 4) + 4 * r;
+                if (n >= nrows) continue;
+                const uint32_t ro = row_off(sbase, h, cstr, n);
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj) {
+                    const int k = tj * 16 + (lane & 15);
+                    if (k >= N) continue;
+                    const size_t idx = ro + coff[k];
+                    Q[idx] = (Tq)dr[tj][r];
+                    Q[idx + cstr] = (Tq)di[tj][r];
                 }
             }
-        }
-        gram_store<NT>(acc, Gp + wave * NP * NP, NP, lane);
-        __syncthreads();
-        // reduce the wavefronts' partial Gram matrices (upper triangle)
-        for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {
-            const int k = e / NP, l = e % NP;
-            if (l < k) continue;
-            Cplx s = Gp[e];
-            for (int w = 1; w < NW; ++w) {
-                s.re += Gp[w * NP * NP + e].re;
-                s.im += Gp[w * NP * NP + e].im;
-            }
-            G[e] = s;
-        }
-        __syncthreads();
-        for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = pass == 0 ? G[k * NP + k].re : 1.0;
-        cholesky_inplace(G, diag0, N, NP, &bad);
-        tri_inverse(G, pass == 0 ? X1 : X2, NP);
-    }
-    tri_product(X1, X2, G, NP);  // G <- R1^-1 R2^-1
-    // Q = V (R1^-1 R2^-1), 16-row blocks spread over the wavefronts
-    for (int b0 = wave * 16; b0 < rows; b0 += NW * 16) {
-        d4 dr[2], di[2];
-        transform_block<NT>(a, i, h, b0, rows, G, NP, lane, dr, di);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = b0 + (lane >> 4) + 4 * r;
-            if (n >= rows) continue;
-            const size_t ro = row_offset(a, i, h, n);
-#pragma unroll
-            for (int tj = 0; tj < NT; ++tj) {
-                const int k = tj * 16 + (lane & 15);
-                if (k >= N) continue;
-                const size_t idx = ro + col_offset(a, k);
-                store_elem(a.Q, a.qdt, idx, dr[tj][r]);
-                store_elem(a.Q, a.qdt, idx + cstr, di[tj][r]);
-            }
+            cur = nxt;
         }
     }
     __syncthreads();
@@ -320,22 +453,37 @@ __global__ void k_status_final(int32_t *s)
     if (*s == INT_MAX) *s = 0;
 }
 
-size_t gs_lds(int NP) { return sizeof(Cplx) * (size_t)(NW + 3) * NP * NP + sizeof(double) * NP; }
+size_t gs_lds(int NP)
+{
+    const size_t uni = std::max(2 * NP * NP, 64 * NP);
+    return sizeof(Cplx) * (NP * NP + uni) + (sizeof(double) + sizeof(size_t)) * NP + 4 * SCH;
+}
 
-template <int NT> int launch_nt(const GsArgs &a, int n_agg, size_t max_lds, hipStream_t st)
+template <typename Tv, typename Tq, int NT> int launch_typed(const GsArgs &a, int n_agg, size_t max_lds, hipStream_t st)
 {
     const size_t lds = gs_lds(NT * 16);
     if (lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "Gram-Schmidt LDS exceeds the workgroup limit");
     static size_t done = 0;
     if (lds > 65536 && lds > done) {
-        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_block_gs<NT>,
+        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_block_gs<Tv, Tq, NT>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                                "hipFuncSetAttribute(gs LDS)"))
             return rc;
         done = lds;
     }
-    hipLaunchKernelGGL(k_block_gs<NT>, dim3(2 * n_agg), dim3(NTHR), lds, st, a);
+    hipLaunchKernelGGL((k_block_gs<Tv, Tq, NT>), dim3(2 * n_agg), dim3(NTHR), lds, st, a);
     return hip_check(hipGetLastError(), "k_block_gs launch");
+}
+
+template <typename Tv, typename Tq> int launch_nt(const GsArgs &a, int n_agg, size_t max_lds, hipStream_t st)
+{
+    return a.n_tv > 16 ? launch_typed<Tv, Tq, 2>(a, n_agg, max_lds, st) : launch_typed<Tv, Tq, 1>(a, n_agg, max_lds, st);
+}
+
+template <typename Tv> int launch_v(const GsArgs &a, int qdt, int n_agg, size_t max_lds, hipStream_t st)
+{
+    return qdt == MRHS_DTYPE_F64 ? launch_nt<Tv, double>(a, n_agg, max_lds, st)
+                                 : launch_nt<Tv, float>(a, n_agg, max_lds, st);
 }
 
 }  // namespace
@@ -350,19 +498,19 @@ int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n
     a.g = op->k;
     a.Va = op->Va;
     a.n_tv = n_tv;
-    a.NT = n_tv > 16 ? 2 : 1;
     a.agg_sites = op->agg_sites;
     a.V = V;
-    a.vdt = vdt;
     a.Q = Q;
-    a.qdt = qdt;
     a.status = status;
     if (!a.agg_sites || !a.V || !a.Q) return set_error(MRHS_EINVAL, "block_orthonormalize: missing buffer");
     if (status) {
         hipLaunchKernelGGL(k_status_init, dim3(1), dim3(1), 0, st, status);
         if (int rc = hip_check(hipGetLastError(), "k_status_init launch")) return rc;
     }
-    int rc = a.NT == 2 ? launch_nt<2>(a, op->n_agg, op->max_lds, st) : launch_nt<1>(a, op->n_agg, op->max_lds, st);
+    int rc;
+    if (vdt == MRHS_DTYPE_F64) rc = launch_v<double>(a, qdt, op->n_agg, op->max_lds, st);
+    else if (vdt == MRHS_DTYPE_F32) rc = launch_v<float>(a, qdt, op->n_agg, op->max_lds, st);
+    else rc = launch_v<__half>(a, qdt, op->n_agg, op->max_lds, st);
     if (rc) return rc;
     if (status) {
         hipLaunchKernelGGL(k_status_final, dim3(1), dim3(1), 0, st, status);

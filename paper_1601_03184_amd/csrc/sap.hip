@@ -1,8 +1,9 @@
 // sap.hip -- the Schwarz alternating procedure on all right-hand sides at once.
 //
-// One launch per colour half-sweep.  Workgroup = one SAP block of that colour x a tile
-// of T right-hand sides; thread (off, t) owns one site of the block and one right-hand
-// side.  The workgroup
+// One launch per colour half-sweep, for one operator or a batch of several (lattices of
+// uneven size, each with its own right-hand sides).  Workgroup = one SAP block of that
+// colour x a tile of T right-hand sides; thread (off, t) owns one site of the block and
+// one right-hand side.  The workgroup
 //   1. forms the residual r = b - D x on its block (full stencil, neighbours from global
 //      memory; skipped where x is known to be zero),
 //   2. runs n_mr minimal-residual steps on the block operator D_j = I_j^T D I_j with the
@@ -214,15 +215,6 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     }
 }
 
-template <typename Ts, typename Tc, int T>
-__global__ void __launch_bounds__(256 * T) k_sap_half(SapArgs<Ts, Tc> a)
-{
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int li = xcd_remap(blockIdx.x, a.nblocks * a.ntiles);
-    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
-    sap_block<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
-}
-
 // Several operators (lattices of uneven size, each with its own right-hand sides) in one
 // launch per half-sweep: workgroup w (after the XCD remap) belongs to the instance whose
 // range [first[k], first[k+1]) holds it.  Descriptors travel by value in the kernel
@@ -270,86 +262,7 @@ template <typename Ts> __global__ void k_fill_zero(Ts *__restrict__ p, long n)
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = Ts(0);
 }
 
-template <typename Ts> __global__ void k_copy(const Ts *__restrict__ s, Ts *__restrict__ d, long n)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
-}
-
 int round64(int n) { return (n + 63) / 64 * 64; }
-
-template <typename Ts, typename Tc, int T> int set_lds(size_t bytes)
-{
-    static size_t done = 0;
-    if (bytes > 65536 && bytes > done) {
-        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_sap_half<Ts, Tc, T>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
-                               "hipFuncSetAttribute(sap LDS)"))
-            return rc;
-        done = bytes;
-    }
-    return MRHS_OK;
-}
-
-template <typename Ts, typename Tc, int T> int launch_half(const SapArgs<Ts, Tc> &a, size_t max_lds, hipStream_t st)
-{
-    const KGeo &g = a.g;
-    const int threads = round64(g.Vb * T);
-    const size_t lds = sizeof(Tc) * (24 * (size_t)g.Vb * T + (size_t)(threads / 64) * T * 3);  // rho pairs + reductions
-    if (lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "SAP tile exceeds the LDS of a workgroup");
-    if (int rc = set_lds<Ts, Tc, T>(lds)) return rc;
-    hipLaunchKernelGGL((k_sap_half<Ts, Tc, T>), dim3(a.nblocks * a.ntiles), dim3(threads), lds, st, a);
-    return hip_check(hipGetLastError(), "k_sap_half launch");
-}
-
-template <typename Ts, typename Tc>
-int sap_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const void *b, void *x, int n_rhs, int n_sap,
-                 int n_mr, void *ws, hipStream_t st)
-{
-    const KGeo &g = op->k;
-    const int T = op->sap_tile;
-    const int ngrp = (n_rhs + g.S - 1) / g.S;
-    const long nel = (long)native_elems(op, n_rhs);
-    if (n_sap == 0) {
-        hipLaunchKernelGGL(k_fill_zero<Ts>, dim3(1024), dim3(256), 0, st, (Ts *)x, nel);
-        return hip_check(hipGetLastError(), "k_fill_zero launch");
-    }
-    SapArgs<Ts, Tc> a{};
-    a.g = g;
-    a.links = links;
-    a.clover = clover;
-    a.blk_coords = op->blk_coords;
-    a.loc_coords = op->loc_coords;
-    a.ntiles = ngrp * (g.S / T);
-    a.n_mr = n_mr;
-    a.b = (const Ts *)b;
-    a.x = (Ts *)x;
-    Ts *snap = (Ts *)ws;
-    for (int s = 0; s < n_sap; ++s)
-        for (int c = 0; c < 2; ++c) {
-            if (op->n_colour[c] == 0) continue;
-            a.colour = c;
-            a.blocks = op->colour_blocks + (c == 0 ? 0 : op->n_colour[0]);
-            a.nblocks = op->n_colour[c];
-            a.mode = s == 0 ? c : 2;
-            a.xr = a.x;
-            if (a.mode == 2 && op->odd_blocks) {
-                // same-coloured blocks touch across the periodic wrap: read neighbours
-                // from a snapshot taken before this colour's updates
-                hipLaunchKernelGGL(k_copy<Ts>, dim3(2048), dim3(256), 0, st, (const Ts *)x, snap, nel);
-                if (int rc = hip_check(hipGetLastError(), "k_copy launch")) return rc;
-                a.xr = snap;
-            }
-            int rc;
-            switch (T) {
-            case 1: rc = launch_half<Ts, Tc, 1>(a, op->max_lds, st); break;
-            case 2: rc = launch_half<Ts, Tc, 2>(a, op->max_lds, st); break;
-            case 4: rc = launch_half<Ts, Tc, 4>(a, op->max_lds, st); break;
-            default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
-            }
-            if (rc) return rc;
-        }
-    return MRHS_OK;
-}
 
 template <typename Tc> const Tc *op_links(const mrhs_op *op);
 template <> const double *op_links<double>(const mrhs_op *op) { return op->links64; }
@@ -480,19 +393,9 @@ int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, v
     }
 }
 
-size_t ws_bytes_sap(const mrhs_op *op, int n_rhs)
-{
-    return op->odd_blocks ? native_elems(op, n_rhs) * dtype_size(op->dtype) : 0;
-}
+size_t ws_bytes_sap(const mrhs_op *op, int n_rhs) { return ws_bytes_sap_batched(&op, 1, &n_rhs); }
 
 int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st)
 {
-    switch (op->prec) {
-    case MRHS_PREC_F64:
-        return sap_dispatch<double, double>(op, op->links64, op->clover64, b, x, n_rhs, n_sap, n_mr, ws, st);
-    case MRHS_PREC_F32:
-        return sap_dispatch<float, float>(op, op->links32, op->clover32, b, x, n_rhs, n_sap, n_mr, ws, st);
-    default:
-        return sap_dispatch<__half, float>(op, op->links32, op->clover32, b, x, n_rhs, n_sap, n_mr, ws, st);
-    }
+    return launch_sap_batched(&op, 1, &b, &x, &n_rhs, n_sap, n_mr, ws, st);
 }

@@ -10,6 +10,9 @@ eigen-decomposition, then re-unitarised (normalise row 0, Gram-Schmidt row 1,
 row 2 = conj(row0 x row1)) so that U is in SU(3) to rounding.  Draw order:
 direction-major, then site, then the 9 real parts, then the 9 imaginary parts.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 _CHUNK = 1 << 18  # links per generation chunk (bounds host memory on big lattices)
@@ -36,12 +39,22 @@ def _su3_from_draws(d, sigma):
 
 
 def random_su3(n, sigma, rng):
-    """n SU(3) matrices from the recipe above, drawing from the Generator rng."""
+    """n SU(3) matrices from the recipe above, drawing from the Generator rng.
+
+    Chunks are drawn in order and turned into matrices on a thread pool (numpy releases
+    the interpreter lock in its array kernels); the result does not depend on the
+    number of threads."""
     out = np.empty((n, 3, 3), np.complex128)
-    for s in range(0, n, _CHUNK):
-        m = min(_CHUNK, n - s)
-        d = rng.standard_normal((m, 2, 3, 3))
-        out[s:s + m] = _su3_from_draws(d, sigma)
+    starts = list(range(0, n, _CHUNK))
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), len(starts)))
+
+    def work(s, d):
+        out[s:s + d.shape[0]] = _su3_from_draws(d, sigma)
+
+    with ThreadPoolExecutor(workers) as ex:
+        for w0 in range(0, len(starts), workers):
+            batch = [(s, rng.standard_normal((min(_CHUNK, n - s), 2, 3, 3))) for s in starts[w0:w0 + workers]]
+            list(ex.map(lambda sd: work(*sd), batch))
     return out
 
 

@@ -108,3 +108,35 @@ def test_coarse_parity(L, block, agg, prec, S, n, qdt):
     for i in range(op.n_agg):
         assert rel(s3 @ got[i, 0], got[i, 0].conj().T @ s3) < 1e-5
     op.close()
+
+
+def coarse_bytes_per_aggregate(L, agg, S, n):
+    """One aggregate's share of the coarse workspace, by the formula in include/mrhs.h."""
+    Va = int(np.prod(agg))
+    sites = Va + sum(Va // a for a in agg)
+    return 4 * 2 * ((n + S - 1) // S) * S * sites * 24
+
+
+@pytest.mark.parametrize("n_slice", [1, 3])
+def test_coarse_small_workspace_slices(n_slice):
+    """A workspace of n_slice aggregates' columns builds D_c in slices; the result equals
+    the one-launch build bit for bit (each block is computed by the same kernels)."""
+    need_gpu()
+    L, block, agg, n, S = [8, 4, 8, 4], [4, 4, 4, 4], [2, 4, 4, 2], 13, 4
+    case = Case(L, 0.3, 311, -0.2)
+    announce("coarse slices of %d aggregates" % n_slice)
+    op = case.op(block, agg=agg, prec=F32, short_len=S)
+    q = oracle.block_gs(L, agg, inputs.test_vectors(L, n, 312))
+    qn = op.pack(torch.from_numpy(q), D32)
+    nc = 2 * n
+    full = torch.zeros(op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+    mrhs.coarse_op_build(op.handle, qn, D32, n, full, op.workspace(n))
+    per = coarse_bytes_per_aggregate(L, agg, S, n)
+    sliced = torch.full_like(full, float("nan"))
+    ws = torch.empty(n_slice * per, dtype=torch.uint8, device="cuda")
+    mrhs.coarse_op_build(op.handle, qn, D32, n, sliced, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(full, sliced)
+    with pytest.raises(mrhs.MrhsError):
+        mrhs.coarse_op_build(op.handle, qn, D32, n, sliced, torch.empty(per - 4, dtype=torch.uint8, device="cuda"))
+    op.close()
