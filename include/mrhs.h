@@ -143,10 +143,7 @@ int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void
  * each 2 n_tv x 2 n_tv complex64 row-major, row = h*n_tv + k.  The self block holds the
  * site term and the hops that stay inside the aggregate without crossing its faces; the
  * +mu (-mu) block holds the hops across the aggregate's +mu (-mu) face.  Dc: DEVICE.
- * ws: mrhs_workspace_bytes(op, n_tv) bytes (at most 1 GiB for this call) builds D_c in
- * the fewest launches; a smaller workspace is used in slices of aggregates, down to one
- * aggregate's columns (2 ceil(n_tv/S) S (Va + sum_mu Va/agg_mu) 24 floats, S the short
- * length, Va the aggregate volume); below that the call returns EINVAL. */
+ * Needs no workspace (ws may be null).  Needs n_tv <= 32. */
 int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc, void *ws,
                     size_t ws_bytes, void *stream);
 

@@ -9,13 +9,12 @@
 // The last line is exact: the -mu face hop of i is the adjoint of the +mu face hop of i-mu
 // conjugated by g5, and g5 acts on the coarse index as sigma3 = diag(1, -1) over halves.
 //
-// k_coarse_cols   : per (aggregate, column c): W0[c] = (A + inside hops) P_c on every site
-//                   and Wf[mu][c] = (1 - g_mu) W_mu P_c(x + mu) on the +mu face sites
-//                   -> workspace
-// k_coarse_blocks : per (aggregate, block d in self,+x..+t) the 2N x 2N product
-//                   sum over sites and half-h components of conj(q_k) w_c, with the sites
-//                   staged through LDS in chunks
-// k_coarse_back   : the four -mu blocks by the sigma3 relation
+// k_coarse      : per (aggregate i, block d in self,+x..+t), the sites of the block's set
+//                 (all sites for self, the +mu face for +mu) in chunks of CHS: the chunk's
+//                 rows conj(q_k) and its columns w_c = (stencil part d) P_c, computed from
+//                 Q on the vector units, go to LDS; the 2N x 2N product accumulates on the
+//                 matrix cores.  Nothing is written to memory but D_c.
+// k_coarse_back : the four -mu blocks by the sigma3 relation
 #include <algorithm>
 
 #include "stencil.h"
@@ -30,14 +29,10 @@ template <typename Tq> struct CoarseArgs {
     KGeo g;
     int a[4], na[4], astr[4];
     int Va, n_agg, N;
-    int agg0, nsl;  // this launch: aggregates agg0 .. agg0 + nsl - 1 (the workspace holds nsl)
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
-    int ngrp;      // groups of S test vectors
-    float *W0;     // [2][ngrp][n_agg][24][Va][S]
-    float *Wf[4];  // [2][ngrp][n_agg][24][Va / a_mu][S]
-    float *Dc;     // [n_agg][9][2N][2N][2]
+    float *Dc;  // [n_agg][9][2N][2N][2]
 };
 
 __device__ inline void agg_local(const int (&a)[4], int ls, int (&lc)[4])
@@ -93,14 +88,6 @@ __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int
     hop_fence(w);
 }
 
-// workspace element of column (h', k' = grp*S + t), aggregate i (of this launch's slice),
-// real component r, site sidx of a set of nsites sites per aggregate
-template <typename Tq>
-__device__ inline size_t wcol_index(const CoarseArgs<Tq> &a, int hp, int grp, int i, int r, int nsites, int sidx, int t)
-{
-    return (((((size_t)hp * a.ngrp + grp) * a.nsl + (i - a.agg0)) * 24 + r) * nsites + sidx) * a.g.S + t;
-}
-
 // local site of the f-th site on the +mu face of an aggregate (local coordinate mu = a_mu - 1)
 __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu, int f)
 {
@@ -108,93 +95,64 @@ __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu,
     return f % st + st * (a[mu] - 1) + st * a[mu] * (f / st);
 }
 
+// column (HP, k') of the self part at aggregate site ls (native ns): (A + inside hops) P_c
+template <int HP, typename Tc, typename Tq>
+__device__ inline void self_column(const CoarseArgs<Tq> &a, const Tc *links, const Tc *clover, int i, int ls, int ns,
+                                   int kp, Spinor<Tc> &w)
+{
+    int lc[4];
+    agg_local(a.a, ls, lc);
+    Spinor<Tc> p;
+    load_pcol<HP, Tc>(a.g, a.Q, kp, ns, p);
+    // the site term is block-diagonal in the spin halves: only half HP is non-zero
+    spinor_zero(w);
+    {
+        Tc A[36];
+        load_clover_half<HP>(clover, a.g.V, ns, A);
+        clover_half<HP>(A, p, w);
+    }
+    hop_fence(w);
+    inside_hops<0, HP>(a, links, i, ls, ns, lc, kp, w);
+    inside_hops<1, HP>(a, links, i, ls, ns, lc, kp, w);
+    inside_hops<2, HP>(a, links, i, ls, ns, lc, kp, w);
+    inside_hops<3, HP>(a, links, i, ls, ns, lc, kp, w);
+}
+
+// column (HP, k') of the +MU face part at face site ns: (1 - g_mu) W_mu P_c(x + mu)
 template <int MU, int HP, typename Tc, typename Tq>
-__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int ls, int kp, int i, int grp,
-                                   int t)
+__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int kp, Spinor<Tc> &w)
 {
     const KGeo &g = a.g;
     const int blk = ns / g.Vb, off = ns - blk * g.Vb;
     int bc[4], lcb[4];
     decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lcb);
     const NbrSite n = nbr_fwd(g, MU, blk, off, bc, lcb);
-    Spinor<Tc> chi, w;
+    Spinor<Tc> chi;
     load_pcol<HP, Tc>(g, a.Q, kp, n.blk * g.Vb + n.off, chi);
     Tc U[18];
     load_link(links, g.V, MU, ns, U);
     spinor_zero(w);
     hop_accumulate<MU, -1, false>(U, chi, w);
-    // index of this site among the face sites: drop local coordinate MU
-    const int st = a.astr[MU];
-    const int f = ls % st + st * (ls / (st * a.a[MU]));
-    const int nf = a.Va / a.a[MU];
-    float *dst = a.Wf[MU];
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        dst[wcol_index(a, HP, grp, i, 2 * q, nf, f, t)] = (float)w.re[q];
-        dst[wcol_index(a, HP, grp, i, 2 * q + 1, nf, f, t)] = (float)w.im[q];
-    }
 }
 
-// grid: (aggregate i, h' * ngrp + group); threads: (site ls, lane t), test vector k' = group*S + t.
-// The S lanes of a site read the S test vectors of a group from one contiguous run.
-template <typename Tc> constexpr int cols_threads() { return sizeof(Tc) == 8 ? 512 : 1024; }
-
+// column (HP, k') of stencil part d (0 self, 1 + mu the +mu face) at site ls / ns
 template <int HP, typename Tc, typename Tq>
-__device__ inline void coarse_cols_half(const CoarseArgs<Tq> &a, const Tc *__restrict__ links,
-                                        const Tc *__restrict__ clover, int i, int grp)
+__device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *links, const Tc *clover, int d, int i, int ls,
+                                   int ns, int kp, Spinor<Tc> &w)
 {
-    const int S = a.g.S;
-    for (int e = threadIdx.x; e < a.Va * S; e += blockDim.x) {
-        const int ls = e / S, t = e - ls * S;
-        const int kp = grp * S + t;
-        const int ns = a.agg_sites[(size_t)i * a.Va + ls];
-        int lc[4];
-        agg_local(a.a, ls, lc);
-        {
-            Spinor<Tc> p, w;
-            load_pcol<HP, Tc>(a.g, a.Q, kp, ns, p);
-            // the site term is block-diagonal in the spin halves: only half HP is non-zero
-            spinor_zero(w);
-            {
-                Tc A[36];
-                load_clover_half<HP>(clover, a.g.V, ns, A);
-                clover_half<HP>(A, p, w);
-            }
-            hop_fence(w);
-            inside_hops<0, HP>(a, links, i, ls, ns, lc, kp, w);
-            inside_hops<1, HP>(a, links, i, ls, ns, lc, kp, w);
-            inside_hops<2, HP>(a, links, i, ls, ns, lc, kp, w);
-            inside_hops<3, HP>(a, links, i, ls, ns, lc, kp, w);
-#pragma unroll
-            for (int q = 0; q < 12; ++q) {
-                a.W0[wcol_index(a, HP, grp, i, 2 * q, a.Va, ls, t)] = (float)w.re[q];
-                a.W0[wcol_index(a, HP, grp, i, 2 * q + 1, a.Va, ls, t)] = (float)w.im[q];
-            }
-        }
-        sched_fence();
-        if (lc[0] == a.a[0] - 1) face_column<0, HP>(a, links, ns, ls, kp, i, grp, t);
-        sched_fence();
-        if (lc[1] == a.a[1] - 1) face_column<1, HP>(a, links, ns, ls, kp, i, grp, t);
-        sched_fence();
-        if (lc[2] == a.a[2] - 1) face_column<2, HP>(a, links, ns, ls, kp, i, grp, t);
-        sched_fence();
-        if (lc[3] == a.a[3] - 1) face_column<3, HP>(a, links, ns, ls, kp, i, grp, t);
+    switch (d) {
+    case 0: self_column<HP>(a, links, clover, i, ls, ns, kp, w); break;
+    case 1: face_column<0, HP>(a, links, ns, kp, w); break;
+    case 2: face_column<1, HP>(a, links, ns, kp, w); break;
+    case 3: face_column<2, HP>(a, links, ns, kp, w); break;
+    default: face_column<3, HP>(a, links, ns, kp, w); break;
     }
-}
-
-template <typename Tc, typename Tq>
-__global__ void __launch_bounds__(cols_threads<Tc>()) k_coarse_cols(CoarseArgs<Tq> a, const Tc *__restrict__ links,
-                                                                      const Tc *__restrict__ clover)
-{
-    const int i = a.agg0 + blockIdx.x;
-    const int hp = blockIdx.y / a.ngrp, grp = blockIdx.y - hp * a.ngrp;
-    if (hp == 0) coarse_cols_half<0>(a, links, clover, i, grp);
-    else coarse_cols_half<1>(a, links, clover, i, grp);
 }
 
 // grid: (aggregate i, block d = 0 self, 1..4 = +mu).  The 2N x 2N block is a sum over the
 // block's sites and the 6 components of each spin half: rows (h, k) = conj(q_k) of half h,
-// columns c = the workspace columns.  Sites are staged through LDS in chunks of CHS; the
+// columns c = (h', k') the stencil part d applied to P_c.  Both are formed a chunk of CHS
+// sites at a time in LDS (the columns by one thread per (h', site, k')); the
 // products run on v_mfma_f32_16x16x4f32: the block is cut into 16x16 tiles (per half:
 // ceil(N/16) x ceil(2N/16)), the wavefronts take tiles round-robin, a K step is 4 of the
 // (site, component) rows, and complex = 4 real products.  Lane l supplies
@@ -203,17 +161,17 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
 
-template <typename Tq>
-__global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
+template <typename Tc, typename Tq>
+__global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__restrict__ links,
+                                                 const Tc *__restrict__ clover)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N, N2 = 2 * N;
     float2 *Qs = reinterpret_cast<float2 *>(smem);  // [CHS][12][N]
     float2 *Ws = Qs + CHS * 12 * N;                // [CHS][12][2N]
-    const int i = a.agg0 + blockIdx.x, d = blockIdx.y;
+    const int i = blockIdx.x, d = blockIdx.y;
     const int mu = d - 1;
     const int nsites = d == 0 ? a.Va : a.Va / a.a[mu];
-    const float *Wsrc = d == 0 ? a.W0 : a.Wf[mu];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int TR = (N + 15) / 16, TC = (N2 + 15) / 16, ntile = 2 * TR * TC;
     constexpr int MAXT = 4;  // tiles per wavefront (N <= 32: at most 16 tiles, 4 wavefronts)
@@ -238,17 +196,23 @@ __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
             }
             Qs[e] = v;
         }
-        for (int e = threadIdx.x; e < CHS * 12 * N2; e += blockDim.x) {
-            const int sl = e / (12 * N2), rem = e - sl * 12 * N2, comp = rem / N2, c = rem - comp * N2;
+        // columns: thread e -> (h', site, k'), k' fastest, so that a wavefront mostly
+        // shares one spin half
+        for (int e = threadIdx.x; e < 2 * CHS * N; e += blockDim.x) {
+            const int hp = e / (CHS * N), rem = e - hp * CHS * N, sl = rem / N, kp = rem - sl * N;
             const int sidx = s0 + sl;
-            float2 v = make_float2(0.f, 0.f);
+            Spinor<Tc> w;
             if (sidx < nsites) {
-                const int hp = c / N, kp = c - hp * N;
-                const int grp = kp / a.g.S, t = kp - grp * a.g.S;
-                v = make_float2(Wsrc[wcol_index(a, hp, grp, i, 2 * comp, nsites, sidx, t)],
-                                Wsrc[wcol_index(a, hp, grp, i, 2 * comp + 1, nsites, sidx, t)]);
+                const int ls = d == 0 ? sidx : face_site(a.a, a.astr, mu, sidx);
+                const int ns = a.agg_sites[(size_t)i * a.Va + ls];
+                if (hp == 0) part_column<0>(a, links, clover, d, i, ls, ns, kp, w);
+                else part_column<1>(a, links, clover, d, i, ls, ns, kp, w);
+            } else {
+                spinor_zero(w);
             }
-            Ws[e] = v;
+            const int c = hp * N + kp;
+#pragma unroll
+            for (int comp = 0; comp < 12; ++comp) Ws[(sl * 12 + comp) * N2 + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
         }
         __syncthreads();
 #pragma unroll
@@ -258,6 +222,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse_blocks(CoarseArgs<Tq> a)
             const int h = tile / (TR * TC), rem = tile - h * TR * TC, tr = rem / TC, tc = rem - tr * TC;
             const int k = tr * 16 + (lane & 15);   // output row within the half (A row)
             const int c = tc * 16 + (lane & 15);   // output column (B column)
+#pragma unroll 1
             for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
                 const int kk = kk0 + (lane >> 4), sl = kk / 6, comp = 6 * h + kk % 6;
                 const float2 q = k < N ? Qs[(sl * 12 + comp) * N + k] : make_float2(0.f, 0.f);
@@ -313,26 +278,9 @@ template <typename Tq> __global__ void k_coarse_back(CoarseArgs<Tq> a)
     }
 }
 
-// workspace columns of one aggregate: the self columns on all its sites and the face
-// columns on its four forward faces
-size_t coarse_bytes_per_agg(const mrhs_op *op, int n_tv)
-{
-    size_t sites = op->Va;
-    for (int mu = 0; mu < 4; ++mu) sites += op->Va / op->g.agg[mu];
-    const size_t cols = (size_t)2 * ((n_tv + op->k.S - 1) / op->k.S) * op->k.S;
-    return sizeof(float) * cols * sites * 24;
-}
-
-// aggregates per launch: as many as fit ws_bytes of workspace (the caller guarantees one)
-int coarse_slice(const mrhs_op *op, int n_tv, size_t ws_bytes)
-{
-    const size_t n = std::max((size_t)1, ws_bytes / coarse_bytes_per_agg(op, n_tv));
-    return (int)std::min(n, (size_t)op->n_agg);
-}
-
 template <typename Tc, typename Tq>
-int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc, void *ws,
-                    size_t ws_bytes, hipStream_t st)
+int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc,
+                    hipStream_t st)
 {
     CoarseArgs<Tq> a{};
     a.g = op->k;
@@ -346,61 +294,33 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.Va = op->Va;
     a.n_agg = op->n_agg;
     a.N = n_tv;
-    a.ngrp = (n_tv + op->k.S - 1) / op->k.S;
     a.agg_sites = op->agg_sites;
     a.blk_coords = op->blk_coords;
     a.loc_coords = op->loc_coords;
     a.Q = Q;
     a.Dc = (float *)Dc;
-    a.W0 = (float *)ws;
-    {
-        const size_t cols = (size_t)2 * a.ngrp * op->k.S;  // padded columns
-        const size_t sl = coarse_slice(op, n_tv, ws_bytes);
-        float *p = a.W0 + cols * sl * op->Va * 24;
-        for (int mu = 0; mu < 4; ++mu) {
-            a.Wf[mu] = p;
-            p += cols * sl * (op->Va / op->g.agg[mu]) * 24;
-        }
-    }
-    if (!a.Q || !a.Dc || !a.W0 || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
+    if (!a.Q || !a.Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
-    const int cthreads = std::min(cols_threads<Tc>(), (op->Va * op->k.S + 63) / 64 * 64);
     const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
-    const int slice = coarse_slice(op, n_tv, ws_bytes);
-    for (int agg0 = 0; agg0 < op->n_agg; agg0 += slice) {
-        a.agg0 = agg0;
-        a.nsl = std::min(slice, op->n_agg - agg0);
-        hipLaunchKernelGGL((k_coarse_cols<Tc, Tq>), dim3(a.nsl, 2 * a.ngrp), dim3(cthreads), 0, st, a, links, clover);
-        if (int rc = hip_check(hipGetLastError(), "k_coarse_cols launch")) return rc;
-        hipLaunchKernelGGL((k_coarse_blocks<Tq>), dim3(a.nsl, 5), dim3(NTHR), lds, st, a);
-        if (int rc = hip_check(hipGetLastError(), "k_coarse_blocks launch")) return rc;
-    }
+    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a, links, clover);
+    if (int rc = hip_check(hipGetLastError(), "k_coarse launch")) return rc;
     hipLaunchKernelGGL((k_coarse_back<Tq>), dim3(op->n_agg, 4), dim3(NTHR), 0, st, a);
     return hip_check(hipGetLastError(), "k_coarse_back launch");
 }
 
 }  // namespace
 
-// the workspace asked for: all aggregates in one launch pair, capped at 1 GiB
-size_t ws_bytes_coarse(const mrhs_op *op, int n_tv)
-{
-    const size_t per = coarse_bytes_per_agg(op, n_tv);
-    return std::max(per, std::min((size_t)op->n_agg * per, (size_t)1 << 30) / per * per);
-}
+size_t ws_bytes_coarse(const mrhs_op *, int) { return 0; }
 
-// the least workspace that works: one aggregate per launch pair
-size_t ws_bytes_coarse_min(const mrhs_op *op, int n_tv) { return coarse_bytes_per_agg(op, n_tv); }
-
-int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, size_t ws_bytes,
-                  hipStream_t st)
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st)
 {
     if (2 * n_tv * 2 * n_tv > 16 * NTHR) return set_error(MRHS_EUNSUPPORTED, "more than 32 test vectors");
     if (op->links32) {
         if (qdt == MRHS_DTYPE_F32)
-            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, ws, ws_bytes, st);
-        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, ws, ws_bytes, st);
+            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, st);
+        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, st);
     }
     if (qdt == MRHS_DTYPE_F32)
-        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, ws, ws_bytes, st);
-    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, ws, ws_bytes, st);
+        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, st);
+    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, st);
 }

@@ -275,8 +275,7 @@ int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, 
 int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st);
 int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *ws,
               hipStream_t st);
-int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, void *ws, size_t ws_bytes,
-                  hipStream_t st);
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st);
 size_t ws_bytes_sap(const mrhs_op *op, int n_rhs);
 size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs);
 int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
@@ -284,6 +283,5 @@ int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, v
 size_t ws_bytes_residual(const mrhs_op *op, int n_rhs);
 size_t ws_bytes_gs(const mrhs_op *op, int n_tv);
 size_t ws_bytes_coarse(const mrhs_op *op, int n_tv);
-size_t ws_bytes_coarse_min(const mrhs_op *op, int n_tv);
 size_t native_elems(const mrhs_op *op, int n_rhs);
 int dtype_size(int dtype);

@@ -95,3 +95,68 @@ def site_coords(L):
         out[:, mu] = s % L[mu]
         s = s // L[mu]
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# Generators on a torch device, for lattices whose inputs are too large to draw on the
+# host in reasonable time (the full-size workloads).  Same distributions as above, with
+# torch's generator of that device; the exponential is a Taylor series instead of an
+# eigen-decomposition (the same matrix up to rounding).
+# ---------------------------------------------------------------------------------------
+
+def _su3_exp_device(A, sigma):
+    """U = exp(i sigma H), H = (A + A^dag)/2 made traceless, re-unitarised as above.
+    exp by scaling and squaring: (sum_{n<=20} (X/4)^n / n!)^4, X = i sigma H."""
+    import torch
+    H = 0.5 * (A + A.conj().transpose(-1, -2))
+    tr = torch.diagonal(H, dim1=-2, dim2=-1).sum(-1).real / 3.0
+    eye = torch.eye(3, dtype=A.dtype, device=A.device)
+    H = H - tr[:, None, None] * eye
+    X = (1j * sigma / 4.0) * H
+    term = eye.expand_as(X).clone()
+    E = term.clone()
+    for n in range(1, 21):
+        term = term @ X / n
+        E = E + term
+    E = E @ E
+    U = E @ E
+    r0 = U[:, 0, :]
+    r0 = r0 / torch.linalg.vector_norm(r0, dim=-1, keepdim=True)
+    r1 = U[:, 1, :]
+    r1 = r1 - (r0.conj() * r1).sum(-1, keepdim=True) * r0
+    r1 = r1 / torch.linalg.vector_norm(r1, dim=-1, keepdim=True)
+    r2 = torch.linalg.cross(r0, r1).conj()
+    return torch.stack([r0, r1, r2], dim=1)
+
+
+def gauge_field_device(L, sigma, seed, device):
+    """Links U_mu(x), complex128 [4][V][3][3] on `device`, canonical site order.  Draws:
+    a generator of that device seeded with `seed`, chunks of 2^22 links in order, each a
+    (m, 2, 3, 3) standard normal tensor (real parts, then imaginary parts)."""
+    import torch
+    V = volume(L)
+    n = 4 * V
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    out = torch.empty((n, 3, 3), dtype=torch.complex128, device=device)
+    chunk = 1 << 22
+    for s in range(0, n, chunk):
+        m = min(chunk, n - s)
+        d = torch.randn((m, 2, 3, 3), generator=gen, dtype=torch.float64, device=device)
+        out[s:s + m] = _su3_exp_device(torch.complex(d[:, 0], d[:, 1]), sigma)
+    return out.reshape(4, V, 3, 3)
+
+
+def test_vectors_device(L, n, seed, device, first=0):
+    """Test vectors first .. first + n - 1 of a set, complex128 [n][V][4][3] on `device`:
+    vector k has re, im ~ N(0,1) from a generator of that device seeded with
+    seed * 1000003 + k, so any subset is reproducible on its own."""
+    import torch
+    V = volume(L)
+    out = torch.empty((n, V, 4, 3), dtype=torch.complex128, device=device)
+    gen = torch.Generator(device=device)
+    for j in range(n):
+        gen.manual_seed(seed * 1000003 + first + j)
+        d = torch.randn((V, 12, 2), generator=gen, dtype=torch.float64, device=device)
+        out[j] = torch.complex(d[..., 0], d[..., 1]).reshape(V, 4, 3)
+    return out

@@ -110,33 +110,21 @@ def test_coarse_parity(L, block, agg, prec, S, n, qdt):
     op.close()
 
 
-def coarse_bytes_per_aggregate(L, agg, S, n):
-    """One aggregate's share of the coarse workspace, by the formula in include/mrhs.h."""
-    Va = int(np.prod(agg))
-    sites = Va + sum(Va // a for a in agg)
-    return 4 * 2 * ((n + S - 1) // S) * S * sites * 24
 
-
-@pytest.mark.parametrize("n_slice", [1, 3])
-def test_coarse_small_workspace_slices(n_slice):
-    """A workspace of n_slice aggregates' columns builds D_c in slices; the result equals
-    the one-launch build bit for bit (each block is computed by the same kernels)."""
+def test_coarse_needs_no_workspace():
+    """coarse_op_build takes no workspace: a null one gives the same D_c bit for bit."""
     need_gpu()
     L, block, agg, n, S = [8, 4, 8, 4], [4, 4, 4, 4], [2, 4, 4, 2], 13, 4
     case = Case(L, 0.3, 311, -0.2)
-    announce("coarse slices of %d aggregates" % n_slice)
+    announce("coarse without workspace")
     op = case.op(block, agg=agg, prec=F32, short_len=S)
     q = oracle.block_gs(L, agg, inputs.test_vectors(L, n, 312))
     qn = op.pack(torch.from_numpy(q), D32)
     nc = 2 * n
-    full = torch.zeros(op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
-    mrhs.coarse_op_build(op.handle, qn, D32, n, full, op.workspace(n))
-    per = coarse_bytes_per_aggregate(L, agg, S, n)
-    sliced = torch.full_like(full, float("nan"))
-    ws = torch.empty(n_slice * per, dtype=torch.uint8, device="cuda")
-    mrhs.coarse_op_build(op.handle, qn, D32, n, sliced, ws)
+    a = torch.zeros(op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+    b = torch.full_like(a, float("nan"))
+    mrhs.coarse_op_build(op.handle, qn, D32, n, a, op.workspace(n))
+    mrhs.coarse_op_build(op.handle, qn, D32, n, b, None)
     torch.cuda.synchronize()
-    assert torch.equal(full, sliced)
-    with pytest.raises(mrhs.MrhsError):
-        mrhs.coarse_op_build(op.handle, qn, D32, n, sliced, torch.empty(per - 4, dtype=torch.uint8, device="cuda"))
+    assert torch.equal(a, b)
     op.close()
