@@ -16,6 +16,7 @@ stencil's HBM roofline, the single-RHS FP64 GPU path for the same SAP (speedup),
 CPU oracle on a bounded sample (baseline only).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +40,28 @@ N_TV, N_SAP, N_MR = 20, 3, 4
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # published, with packed FP32 FMA
 FP32_ISSUE_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, no packed FP32
+# HBM traffic of the dominant kernel (SAP half-sweep, 16^4, N_tv 20, FP32), per launch and
+# execution tile: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
+# half-sweeps of the bench's calls), each scaled by what the counter reads for a plain 1 GiB
+# device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel sources they were taken
+# with (SHA-1 of the files below); otherwise the bench reports traffic as null.
+SAP_SOURCES = ["paper_1601_03184_amd/csrc/sap.hip", "paper_1601_03184_amd/csrc/stencil.h",
+               "paper_1601_03184_amd/csrc/internal.h"]
+SAP_TRAFFIC = {"sources_sha1": "c75333a1fdcf6faeb7f3b4dd04b4a895461e91bd", "fetch_scale": 2.0, "write_scale": 1.0,
+               "kib": {1: (193676, 86301), 2: (189023, 64740), 4: (208262, 71680)}}
+
+
+def sap_traffic_bytes(tile):
+    h = hashlib.sha1()
+    for f in SAP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != SAP_TRAFFIC["sources_sha1"] or tile not in SAP_TRAFFIC["kib"]:
+        return None
+    fk, wk = SAP_TRAFFIC["kib"][tile]
+    return (fk * SAP_TRAFFIC["fetch_scale"] + wk * SAP_TRAFFIC["write_scale"]) * 1024
+
+
 WORKLOAD = ("16^4 Wilson-clover (sigma=0.3 links, m0=-0.3, csw=1), N_tv=20, SAP 4^4 blocks 3x4 FP32, "
             "FP64 residual check, FP64 block Gram-Schmidt on 4^4 aggregates, D_c FP32")
 
@@ -277,8 +300,9 @@ def main():
     flops_launch = sap_flops_per_call(V, N_TV, N_SAP, N_MR, BLOCK) / n_launch
     achieved = flops_launch / (sap_launch_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
-            "kernel": "k_sap_half (FP32, tile %d)" % tiles["sap"], "launch_ms": round(sap_launch_ms, 4),
+            "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": sap_traffic_bytes(tiles["sap"]),
+            "traffic_unit": "bytes per launch (HBM, counters)", "alg_bytes": round(sap_bytes_per_call(V, N_TV, N_SAP, 4, 4) / n_launch),
+            "kernel": "k_sap_batched (FP32, tile %d)" % tiles["sap"], "launch_ms": round(sap_launch_ms, 4),
             "frac_of_issue_peak": round(achieved / FP32_ISSUE_PEAK_TFLOPS, 4)}
 
     # stencil HBM roofline (the HBM-bound kernel of the path)

@@ -14,7 +14,9 @@
 //                 rows conj(q_k) and its columns w_c = (stencil part d) P_c, computed from
 //                 Q on the vector units, go to LDS; the 2N x 2N product accumulates on the
 //                 matrix cores.  Nothing is written to memory but D_c.
-// k_coarse_back : the four -mu blocks by the sigma3 relation
+//                 The self block is split over NQ workgroups (quarters of the sites).
+// k_coarse_finish: the self block from the quarters, then the four -mu blocks by the
+//                 sigma3 relation
 #include <algorithm>
 
 #include "stencil.h"
@@ -24,6 +26,7 @@ namespace {
 constexpr int NTHR = 256;
 constexpr int NW = NTHR / 64;
 constexpr int CHS = 8;  // sites per LDS chunk
+constexpr int NQ = 4;   // workgroups sharing the self block of an aggregate
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
@@ -149,7 +152,7 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *links, con
     }
 }
 
-// grid: (aggregate i, block d = 0 self, 1..4 = +mu).  The 2N x 2N block is a sum over the
+// grid: (aggregate i, part: NQ quarters of self, then +mu).  A 2N x 2N block is a sum over the
 // block's sites and the 6 components of each spin half: rows (h, k) = conj(q_k) of half h,
 // columns c = (h', k') the stencil part d applied to P_c.  Both are formed a chunk of CHS
 // sites at a time in LDS (the columns by one thread per (h', site, k')); the
@@ -169,9 +172,13 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     const int N = a.N, N2 = 2 * N;
     float2 *Qs = reinterpret_cast<float2 *>(smem);  // [CHS][12][N]
     float2 *Ws = Qs + CHS * 12 * N;                // [CHS][12][2N]
-    const int i = blockIdx.x, d = blockIdx.y;
-    const int mu = d - 1;
-    const int nsites = d == 0 ? a.Va : a.Va / a.a[mu];
+    // blockIdx.y < NQ: quarter q of the self part (partial sum into a -mu slot, summed by
+    // k_coarse_finish); NQ + mu: the +mu face block
+    const int i = blockIdx.x, q = blockIdx.y;
+    const bool self = q < NQ;
+    const int mu = q - NQ, d = self ? 0 : 1 + mu;
+    const int sbeg = self ? q * a.Va / NQ : 0;
+    const int nsites = self ? (q + 1) * a.Va / NQ - sbeg : a.Va / a.a[mu];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int TR = (N + 15) / 16, TC = (N2 + 15) / 16, ntile = 2 * TR * TC;
     constexpr int MAXT = 4;  // tiles per wavefront (N <= 32: at most 16 tiles, 4 wavefronts)
@@ -186,7 +193,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             const int sidx = s0 + sl;
             float2 v = make_float2(0.f, 0.f);
             if (sidx < nsites) {
-                const int ls = d == 0 ? sidx : face_site(a.a, a.astr, mu, sidx);
+                const int ls = self ? sbeg + sidx : face_site(a.a, a.astr, mu, sidx);
                 const int ns = a.agg_sites[(size_t)i * a.Va + ls];
                 const int blk = ns / a.g.Vb, off = ns - blk * a.g.Vb;
                 const int grp = k / a.g.S, t = k - grp * a.g.S;
@@ -203,7 +210,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             const int sidx = s0 + sl;
             Spinor<Tc> w;
             if (sidx < nsites) {
-                const int ls = d == 0 ? sidx : face_site(a.a, a.astr, mu, sidx);
+                const int ls = self ? sbeg + sidx : face_site(a.a, a.astr, mu, sidx);
                 const int ns = a.agg_sites[(size_t)i * a.Va + ls];
                 if (hp == 0) part_column<0>(a, links, clover, d, i, ls, ns, kp, w);
                 else part_column<1>(a, links, clover, d, i, ls, ns, kp, w);
@@ -235,7 +242,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             }
         }
     }
-    float *out = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
+    float *out = a.Dc + ((size_t)i * 9 + (self ? 5 + q : d)) * N2 * N2 * 2;
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) {
         const int tile = wave + NW * m;
@@ -254,27 +261,37 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     }
 }
 
-// D_c(i, i - mu) = sigma3 D_c(i - mu, i)^dag sigma3 ; grid (aggregate, mu)
-template <typename Tq> __global__ void k_coarse_back(CoarseArgs<Tq> a)
+// per aggregate: the self block = the NQ partial sums (kept in the -mu slots), added in a
+// fixed order; then D_c(i, i - mu) = sigma3 D_c(i - mu, i)^dag sigma3 into those slots
+template <typename Tq> __global__ void k_coarse_finish(CoarseArgs<Tq> a)
 {
-    const int i = blockIdx.x, mu = blockIdx.y;
+    const int i = blockIdx.x;
     const int N2 = 2 * a.N, nout = N2 * N2;
-    int c[4], r = i;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        c[m] = r % a.na[m];
-        r /= a.na[m];
+    float *blocks = a.Dc + (size_t)i * 9 * nout * 2;
+    for (int e = threadIdx.x; e < 2 * nout; e += blockDim.x) {
+        float v = blocks[(size_t)5 * nout * 2 + e];
+        for (int p = 1; p < NQ; ++p) v += blocks[(size_t)(5 + p) * nout * 2 + e];
+        blocks[e] = v;
     }
-    c[mu] = (c[mu] - 1 + a.na[mu]) % a.na[mu];
-    const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
-    const float *src = a.Dc + ((size_t)j * 9 + 1 + mu) * nout * 2;
-    float *dst = a.Dc + ((size_t)i * 9 + 5 + mu) * nout * 2;
-    for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-        const int row = e / N2, col = e - row * N2;
-        const float s = ((row < a.N) == (col < a.N)) ? 1.f : -1.f;
-        const int t = col * N2 + row;
-        dst[2 * e] = s * src[2 * t];
-        dst[2 * e + 1] = -s * src[2 * t + 1];
+    __syncthreads();
+    for (int mu = 0; mu < 4; ++mu) {
+        int c[4], r = i;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            c[m] = r % a.na[m];
+            r /= a.na[m];
+        }
+        c[mu] = (c[mu] - 1 + a.na[mu]) % a.na[mu];
+        const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
+        const float *src = a.Dc + ((size_t)j * 9 + 1 + mu) * nout * 2;
+        float *dst = blocks + (size_t)(5 + mu) * nout * 2;
+        for (int e = threadIdx.x; e < nout; e += blockDim.x) {
+            const int row = e / N2, col = e - row * N2;
+            const float s = ((row < a.N) == (col < a.N)) ? 1.f : -1.f;
+            const int t = col * N2 + row;
+            dst[2 * e] = s * src[2 * t];
+            dst[2 * e + 1] = -s * src[2 * t + 1];
+        }
     }
 }
 
@@ -302,10 +319,10 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     if (!a.Q || !a.Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
     const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
-    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a, links, clover);
+    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, NQ + 4), dim3(NTHR), lds, st, a, links, clover);
     if (int rc = hip_check(hipGetLastError(), "k_coarse launch")) return rc;
-    hipLaunchKernelGGL((k_coarse_back<Tq>), dim3(op->n_agg, 4), dim3(NTHR), 0, st, a);
-    return hip_check(hipGetLastError(), "k_coarse_back launch");
+    hipLaunchKernelGGL((k_coarse_finish<Tq>), dim3(op->n_agg), dim3(NTHR), 0, st, a);
+    return hip_check(hipGetLastError(), "k_coarse_finish launch");
 }
 
 }  // namespace
