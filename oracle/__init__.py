@@ -52,6 +52,7 @@ def lib():
             "oracle_block_gs": (i, [p, p, p, i, p, p]),
             "oracle_restrict": (None, [p, p, p, i, p, p, i]),
             "oracle_prolong": (None, [p, p, p, i, p, p, i]),
+            "oracle_coarse_apply": (None, [p, p, p, i, p, p, i]),
             "oracle_coarse_op": (None, [p, p, p, p, p, i, p, p, l]),
         }
         for name, (res, args) in sig.items():
@@ -194,6 +195,19 @@ def prolong(L, a, Q, yc):
     y = np.zeros((n, volume(L), 4, 3), np.complex128)
     lib().oracle_prolong(_ptr(L), _ptr(a), _ptr(Q), n_tv, _ptr(yc), _ptr(y), n)
     return y
+
+
+def coarse_apply(L, a, Dc, yc):
+    """y_c -> D_c y_c on the coarse lattice from the 9 blocks per coarse site (the operator
+    of the coarse solve, Alg. 1); yc [n][Vc][2][n_tv]."""
+    L, a = _ext(L), _ext(a)
+    Dc = _c128(Dc)
+    yc = _c128(yc)
+    nc = Dc.shape[-1]
+    n = yc.size // (n_aggregates(L, a) * nc)
+    out = np.zeros_like(yc)
+    lib().oracle_coarse_apply(_ptr(L), _ptr(a), _ptr(Dc), nc // 2, _ptr(yc), _ptr(out), n)
+    return out
 
 
 def coarse_op(L, a, U, A, Q, agg_list=None):

@@ -713,3 +713,44 @@ void oracle_coarse_op(const int *L, const int *a, const double *U_, const double
     }
     free(P);
 }
+
+/* y_out = D_c y_in on the coarse lattice (the coarse-grid operator applied in the coarse
+ * solve of the setup's refinement phase, Alg. 1): per coarse site i,
+ *   y_out(i) = Dc[i][self] y_in(i) + sum_mu ( Dc[i][+mu] y_in(i+mu) + Dc[i][-mu] y_in(i-mu) ),
+ * neighbours periodic on the coarse lattice L/a (coinciding neighbours are separate
+ * terms).  Coarse vectors [n_rhs][Vc][2 n_tv] complex, blocks [Vc][9][2 n_tv][2 n_tv]. */
+void oracle_coarse_apply(const int *L, const int *a, const double *Dc_, int n_tv, const double *yin_, double *yout_,
+                         int n_rhs)
+{
+    const cplx *Dc = (const cplx *)Dc_;
+    int na[4];
+    block_counts(L, a, na);
+    long Vc = (long)na[0] * na[1] * na[2] * na[3];
+    int nc = 2 * n_tv;
+    for (int r = 0; r < n_rhs; ++r) {
+        const cplx *yin = (const cplx *)yin_ + (long)r * Vc * nc;
+        cplx *yout = (cplx *)yout_ + (long)r * Vc * nc;
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < Vc; ++i) {
+            int c[4];
+            long rem = i;
+            for (int mu = 0; mu < 4; ++mu) {
+                c[mu] = (int)(rem % na[mu]);
+                rem /= na[mu];
+            }
+            for (int row = 0; row < nc; ++row) yout[i * nc + row] = 0;
+            for (int d = 0; d < 9; ++d) {
+                int cn[4] = {c[0], c[1], c[2], c[3]};
+                if (d >= 1 && d <= 4) cn[d - 1] = (cn[d - 1] + 1) % na[d - 1];
+                if (d >= 5) cn[d - 5] = (cn[d - 5] - 1 + na[d - 5]) % na[d - 5];
+                long j = cn[0] + (long)na[0] * (cn[1] + (long)na[1] * (cn[2] + (long)na[2] * cn[3]));
+                const cplx *blk = Dc + (i * 9 + d) * nc * nc;
+                for (int row = 0; row < nc; ++row) {
+                    cplx s = 0;
+                    for (int col = 0; col < nc; ++col) s += blk[row * nc + col] * yin[j * nc + col];
+                    yout[i * nc + row] += s;
+                }
+            }
+        }
+    }
+}

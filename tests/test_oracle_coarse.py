@@ -100,6 +100,22 @@ def test_T17_galerkin(setup_vectors):
     assert rel(got, expect) < 1e-13
 
 
+@pytest.mark.parametrize("L,a", [(L4, A2), ([4, 4, 2, 4], [2, 4, 2, 2])])
+def test_T17_oracle_coarse_apply(L, a):
+    """The oracle's coarse apply (the operator of the coarse solve) equals R D P on random
+    coarse vectors, including coarse extents 1 and 2 where neighbours coincide."""
+    U = inputs.gauge_field(L, 0.3, 211)
+    A = oracle.clover(L, U, 1.0, -0.2)
+    Q = oracle.block_gs(L, a, inputs.test_vectors(L, 4, 212))
+    Dc = oracle.coarse_op(L, a, U, A, Q)
+    Vc = oracle.n_aggregates(L, a)
+    rng = np.random.default_rng(213)
+    yc = rng.standard_normal((3, Vc, 2, 4)) + 1j * rng.standard_normal((3, Vc, 2, 4))
+    expect = oracle.restrict(L, a, Q, oracle.dirac(L, U, A, oracle.prolong(L, a, Q, yc)))
+    got = oracle.coarse_apply(L, a, Dc, yc)
+    assert rel(got, expect) < 1e-13
+
+
 def test_T18_sigma3_symmetry(setup_vectors):
     U, A, V = setup_vectors
     Q = oracle.block_gs(L4, A2, V)
