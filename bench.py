@@ -217,6 +217,30 @@ def batched_bench(reps=5):
             "batched_updates_per_s": upd / (t_b * 1e-3), "graph_updates_per_s": upd / (t_g * 1e-3)}
 
 
+def coarse_grid_bench(mr, reps=20):
+    """The coarse-grid correction's building blocks (refinement phase, Alg. 2) on the step's
+    Q and D_c, applied to the N_tv test vectors at once: restriction (Alg. 3), prolongation
+    and the coarse-operator apply.  Algorithmic bytes: restriction and prolongation read Q
+    and the fine vectors (or write them) once, FP32; the coarse apply reads D_c once and the
+    coarse vectors of the site and its 8 neighbours."""
+    op, n = mr.op, mr.n
+    yc, zc = op.coarse_empty(n, n), op.coarse_empty(n, n)
+    y = op.empty(n)
+    mrhs.restrict_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, mr.x, op.dtype, yc, n)
+    t_r = time_call(lambda: mrhs.restrict_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, mr.x, op.dtype, yc, n), reps)
+    t_p = time_call(lambda: mrhs.prolong_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, yc, y, op.dtype, n), reps)
+    t_a = time_call(lambda: mrhs.coarse_apply_mrhs(op.handle, mr.Dc, n, yc, zc, n), reps)
+    V = int(np.prod(L))
+    fine = V * 24 * 4 * n                       # n FP32 fine vectors
+    coarse = op.n_agg * 2 * n * 2 * 4 * n       # n FP32 coarse vectors
+    dcb = op.n_agg * 9 * (2 * n) ** 2 * 8
+    out = {}
+    for name, ms, b in (("restrict", t_r, 2 * fine + coarse), ("prolong", t_p, 2 * fine + coarse),
+                        ("coarse_apply", t_a, dcb + 10 * coarse)):
+        out[name] = {"ms": round(ms, 4), "alg_GBs": round(b / ms / 1e6, 1), "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def cpu_baseline(U, v, x_gpu, budget_s=30.0):
     """The oracle on the host cores: SAP on a sample of test vectors (they are independent),
     Gram-Schmidt on all aggregates, D_c on a sample of aggregates; scaled to the full step."""
@@ -332,6 +356,10 @@ def main():
         s1.op.close()
         m64.op.close()
 
+    log("coarse-grid building blocks")
+    coarse_grid = coarse_grid_bench(mr)
+    log("coarse grid %s" % coarse_grid)
+
     batched = None
     if not args.no_batched:
         log("batched uneven lattices")
@@ -367,6 +395,7 @@ def main():
         "stencil_roofline": stencil,
         "sap": sap_info,
         "srhs": srhs,
+        "coarse_grid": coarse_grid,
         "batched": batched,
         "cpu_baseline": cpu,
     }

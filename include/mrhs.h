@@ -122,6 +122,12 @@ int dirac_apply_mrhs(const mrhs_op *op, const void *x, void *y, int32_t n_rhs, v
 int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
                     void *ws, size_t ws_bytes, void *stream);
 
+/* As sap_smooth_mrhs, but x holds the starting guess on entry (the refinement phase of the
+ * setup, Alg. 1 and 2: the smoother starts from the prolongated coarse-grid solution); every
+ * half-sweep forms the full residual.  With n_sap = 0, x is left as it is. */
+int sap_smooth_mrhs_guess(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
+                          void *ws, size_t ws_bytes, void *stream);
+
 /* out[k] = ||b_k - D x_k||_2 / ||b_k||_2 in FP64 (FP64 fields, x and b up-converted from
  * their storage type).  out: DEVICE double[n_rhs]. */
 int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out, void *ws,
@@ -146,6 +152,31 @@ int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void
  * Needs no workspace (ws may be null).  Needs n_tv <= 32. */
 int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc, void *ws,
                     size_t ws_bytes, void *stream);
+
+/* ---- coarse-grid correction of the refinement phase (Alg. 1, 2; restriction Alg. 3) ----
+ * Coarse vectors: FP32 on the coarse lattice L/agg (Vc = number of aggregates, sites
+ * lexicographic), element (rhs k, coarse site i, coarse dof c = h*n_tv + j, re/im p) at
+ * ((i * 2*n_tv + c) * 2 + p) * ldc + k, ldc = n_rhs rounded up to a multiple of 4; the
+ * kernels write the padding entries k >= n_rhs as zero.  Arithmetic is FP32 (matrix cores,
+ * FP32 accumulation).  1 <= n_tv, n_rhs <= 32.  Q: the output of block_orthonormalize
+ * (q_dtype F32 or F64). */
+size_t mrhs_coarse_vector_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs);
+
+/* y_c = R y, R = Q^dag per aggregate and spin half: (y_c)^h_i[j] = sum_n conj(Q^h_i[n, j]) y^h_i[n]
+ * (Alg. 3).  y: n_rhs native vectors of y_dtype; yc: DEVICE coarse vectors (output). */
+int restrict_mrhs(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, const void *y, int32_t y_dtype,
+                  float *yc, int32_t n_rhs, void *stream);
+
+/* y = P y_c, P = Q = R^dag (Sec. 2): y^h_i[n] = sum_j Q^h_i[n, j] (y_c)^h_i[j].  y: n_rhs
+ * native vectors of y_dtype (output; the padding lanes of its last group are written zero). */
+int prolong_mrhs(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, const float *yc, void *y,
+                 int32_t y_dtype, int32_t n_rhs, void *stream);
+
+/* yc_out = D_c yc (the coarse operator of the coarse solve): per coarse site,
+ * Dc[i][self] yc(i) + sum_mu (Dc[i][+mu] yc(i+mu) + Dc[i][-mu] yc(i-mu)), neighbours periodic
+ * on the coarse lattice; Dc as written by coarse_op_build.  yc_out must not overlap yc or Dc. */
+int coarse_apply_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const float *yc, float *yc_out,
+                      int32_t n_rhs, void *stream);
 
 /* SAP on several operators at once -- lattices of uneven size, each with its own
  * right-hand sides -- with one launch per half-sweep for the whole batch (the loop over

@@ -53,6 +53,8 @@ def lib():
             "oracle_restrict": (None, [p, p, p, i, p, p, i]),
             "oracle_prolong": (None, [p, p, p, i, p, p, i]),
             "oracle_coarse_apply": (None, [p, p, p, i, p, p, i]),
+            "oracle_sap_from": (i, [p, p, p, p, p, p, i, i, i]),
+            "oracle_coarse_gmres": (None, [p, p, p, i, p, p, i, i, ctypes.c_double, p, p]),
             "oracle_coarse_op": (None, [p, p, p, p, p, i, p, p, l]),
         }
         for name, (res, args) in sig.items():
@@ -134,12 +136,18 @@ def mr(L, b, U, A, j, r, n_mr):
     return e, norms
 
 
-def sap(L, b, U, A, rhs, n_sap, n_mr):
-    """x = SAP(rhs) from a zero start (the initial setup phase of Sec. 2), per vector."""
+def sap(L, b, U, A, rhs, n_sap, n_mr, x0=None):
+    """x = SAP(rhs) per vector, from a zero start (the initial setup phase of Sec. 2) or from
+    the starting guess x0 (the refinement phase, Alg. 1 and 2)."""
     L, b = _ext(L), _ext(b)
     rhs, n = _vecs(rhs, L)
-    x = np.zeros_like(rhs)
-    rc = lib().oracle_sap(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(rhs), _ptr(x), n, int(n_sap), int(n_mr))
+    if x0 is None:
+        x = np.zeros_like(rhs)
+        fn = lib().oracle_sap
+    else:
+        x = np.array(_c128(x0), copy=True).reshape(rhs.shape)
+        fn = lib().oracle_sap_from
+    rc = fn(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(rhs), _ptr(x), n, int(n_sap), int(n_mr))
     if rc != 0:
         raise ValueError("oracle_sap: bad geometry")
     return x
@@ -208,6 +216,23 @@ def coarse_apply(L, a, Dc, yc):
     out = np.zeros_like(yc)
     lib().oracle_coarse_apply(_ptr(L), _ptr(a), _ptr(Dc), nc // 2, _ptr(yc), _ptr(out), n)
     return out
+
+
+def coarse_gmres(L, a, Dc, bc, m, tol=0.0):
+    """u_c ~ D_c^-1 b_c by GMRES from zero, at most m iterations, per right-hand side stopped
+    at residual estimate tol * ||b_c|| (the low-accuracy coarse solve, Alg. 1).
+    Returns (u_c, relative residual estimates, iteration counts)."""
+    L, a = _ext(L), _ext(a)
+    Dc = _c128(Dc)
+    bc = _c128(bc)
+    nc = Dc.shape[-1]
+    n = bc.size // (n_aggregates(L, a) * nc)
+    u = np.zeros_like(bc)
+    res = np.zeros(n)
+    its = np.zeros(n, np.int32)
+    lib().oracle_coarse_gmres(_ptr(L), _ptr(a), _ptr(Dc), nc // 2, _ptr(bc), _ptr(u), n, int(m), float(tol), _ptr(res),
+                              _ptr(its))
+    return u, res, its
 
 
 def coarse_op(L, a, U, A, Q, agg_list=None):

@@ -435,8 +435,11 @@ void oracle_mr(const int *L, const int *b, const double *U_, const double *A_, l
 /* x = SAP(b) from x = 0: n_sap sweeps; each sweep visits colour 0 (red) then
  * colour 1 (black).  Per colour: r = b - D x on the colour's blocks, then every
  * block j of that colour adds MR(D_j, r|_j, n_mr) to x|_j, all from the same r. */
-int oracle_sap(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_, double *x_out_,
-               int n_rhs, int n_sap, int n_mr)
+/* SAP from a given starting guess: x_io holds x0 on entry and the result on exit (the
+ * refinement phase of the setup, Alg. 1 and 2: the smoother starts from the coarse-grid
+ * correction).  oracle_sap below is the start from zero of the initial phase. */
+int oracle_sap_from(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_,
+                    double *x_io_, int n_rhs, int n_sap, int n_mr)
 {
     const cplx *U = (const cplx *)U_, *A = (const cplx *)A_;
     long V = volume(L), Vb = (long)b[0] * b[1] * b[2] * b[3];
@@ -448,8 +451,7 @@ int oracle_sap(const int *L, const int *b, const double *U_, const double *A_, c
     cplx *r = malloc(12 * V * sizeof(cplx));
     for (int k = 0; k < n_rhs; ++k) {
         const cplx *bv = (const cplx *)b_in_ + (long)k * 12 * V;
-        cplx *x = (cplx *)x_out_ + (long)k * 12 * V;
-        for (long i = 0; i < 12 * V; ++i) x[i] = 0;
+        cplx *x = (cplx *)x_io_ + (long)k * 12 * V;
         for (int s = 0; s < n_sap; ++s)
             for (int colour = 0; colour < 2; ++colour) {
 #pragma omp parallel for schedule(static)
@@ -479,6 +481,14 @@ int oracle_sap(const int *L, const int *b, const double *U_, const double *A_, c
     }
     free(r);
     return 0;
+}
+
+int oracle_sap(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_, double *x_out_,
+               int n_rhs, int n_sap, int n_mr)
+{
+    long V = volume(L);
+    for (long i = 0; i < (long)n_rhs * 24 * V; ++i) x_out_[i] = 0;
+    return oracle_sap_from(L, b, U_, A_, b_in_, x_out_, n_rhs, n_sap, n_mr);
 }
 
 /* rel[k] = ||b_k - D x_k|| / ||b_k|| */
@@ -752,5 +762,101 @@ void oracle_coarse_apply(const int *L, const int *a, const double *Dc_, int n_tv
                 }
             }
         }
+    }
+}
+
+/* u = approximate D_c^-1 b on the coarse lattice (the low-accuracy coarse solve of the
+ * refinement phase, Alg. 1), per right-hand side: GMRES from a zero start, at most m
+ * iterations, Arnoldi with classical Gram-Schmidt applied twice, complex Givens rotations
+ * (c real) on the Hessenberg matrix; a right-hand side stops once its residual estimate
+ * |g_{j+1}| falls to tol * ||b|| (tol = 0: exactly m iterations, or fewer on breakdown).
+ * res_out[k] (nullable) = final |g_J| / ||b||, iters_out[k] (nullable) = J.
+ * Coarse vectors [n_rhs][Vc][2 n_tv]. */
+void oracle_coarse_gmres(const int *L, const int *a, const double *Dc_, int n_tv, const double *b_, double *u_,
+                         int n_rhs, int m, double tol, double *res_out, int *iters_out)
+{
+    int na[4];
+    block_counts(L, a, na);
+    long Vc = (long)na[0] * na[1] * na[2] * na[3];
+    long dim = Vc * 2 * n_tv;
+    for (int k = 0; k < n_rhs; ++k) {
+        const cplx *b = (const cplx *)b_ + (long)k * dim;
+        cplx *u = (cplx *)u_ + (long)k * dim;
+        cplx *Vb = calloc((size_t)(m + 1) * dim, sizeof(cplx));
+        cplx *w = malloc(dim * sizeof(cplx));
+        cplx *H = calloc((size_t)(m + 1) * m, sizeof(cplx)); /* H[i][j] at i * m + j */
+        cplx *g = calloc((size_t)(m + 1), sizeof(cplx)), *sn = calloc((size_t)m, sizeof(cplx));
+        double *cs = calloc((size_t)m, sizeof(double));
+        double beta = 0;
+        for (long e = 0; e < dim; ++e) beta += creal(conj(b[e]) * b[e]);
+        beta = sqrt(beta);
+        for (long e = 0; e < dim; ++e) u[e] = 0;
+        int J = 0;
+        double est = beta;
+        if (beta > 0) {
+            for (long e = 0; e < dim; ++e) Vb[e] = b[e] / beta;
+            g[0] = beta;
+            for (int j = 0; j < m; ++j) {
+                if (!(est > tol * beta)) break;
+                oracle_coarse_apply(L, a, Dc_, n_tv, (const double *)(Vb + (long)j * dim), (double *)w, 1);
+                for (int pass = 0; pass < 2; ++pass) {
+                    cplx h[65];
+                    for (int i = 0; i <= j; ++i) {
+                        cplx s = 0;
+                        for (long e = 0; e < dim; ++e) s += conj(Vb[(long)i * dim + e]) * w[e];
+                        h[i] = s;
+                    }
+                    for (int i = 0; i <= j; ++i) {
+                        for (long e = 0; e < dim; ++e) w[e] -= h[i] * Vb[(long)i * dim + e];
+                        H[(long)i * m + j] += h[i];
+                    }
+                }
+                double nw = 0;
+                for (long e = 0; e < dim; ++e) nw += creal(conj(w[e]) * w[e]);
+                nw = sqrt(nw);
+                H[(long)(j + 1) * m + j] = nw;
+                if (nw > 0)
+                    for (long e = 0; e < dim; ++e) Vb[(long)(j + 1) * dim + e] = w[e] / nw;
+                /* earlier rotations on column j, then a new one that zeroes H[j+1][j] */
+                for (int i = 0; i < j; ++i) {
+                    cplx x0 = H[(long)i * m + j], x1 = H[(long)(i + 1) * m + j];
+                    H[(long)i * m + j] = cs[i] * x0 + sn[i] * x1;
+                    H[(long)(i + 1) * m + j] = -conj(sn[i]) * x0 + cs[i] * x1;
+                }
+                cplx hj = H[(long)j * m + j];
+                double ah = cabs(hj), rho = sqrt(ah * ah + nw * nw);
+                if (ah == 0) {
+                    cs[j] = 0;
+                    sn[j] = 1;
+                } else {
+                    cs[j] = ah / rho;
+                    sn[j] = (hj / ah) * nw / rho;
+                }
+                H[(long)j * m + j] = cs[j] * hj + sn[j] * nw;
+                H[(long)(j + 1) * m + j] = 0;
+                g[j + 1] = -conj(sn[j]) * g[j];
+                g[j] = cs[j] * g[j];
+                est = cabs(g[j + 1]);
+                J = j + 1;
+                if (!(nw > 0)) break; /* invariant subspace: the solution is exact */
+            }
+            /* H[0..J)[0..J) y = g[0..J), back substitution; u = sum y_i V_i */
+            cplx y[64];
+            for (int i = J - 1; i >= 0; --i) {
+                cplx s = g[i];
+                for (int l = i + 1; l < J; ++l) s -= H[(long)i * m + l] * y[l];
+                y[i] = s / H[(long)i * m + i];
+            }
+            for (int i = 0; i < J; ++i)
+                for (long e = 0; e < dim; ++e) u[e] += y[i] * Vb[(long)i * dim + e];
+        }
+        if (res_out) res_out[k] = beta > 0 ? est / beta : 0;
+        if (iters_out) iters_out[k] = J;
+        free(Vb);
+        free(w);
+        free(H);
+        free(g);
+        free(sn);
+        free(cs);
     }
 }

@@ -305,8 +305,10 @@ int dirac_apply_mrhs(const mrhs_op *op, const void *x, void *y, int32_t n_rhs, v
     return launch_dirac(op, x, y, n_rhs, (hipStream_t)stream);
 }
 
-int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr, void *ws,
-                    size_t ws_bytes, void *stream)
+namespace {
+
+int sap_common(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr, void *ws,
+               size_t ws_bytes, void *stream, bool guess)
 {
     if (int rc = check_op(op)) return rc;
     if (int rc = check_nrhs(n_rhs)) return rc;
@@ -318,7 +320,21 @@ int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, in
     if (need && (!ws || ws_bytes < need)) return set_error(MRHS_EINVAL, "workspace too small");
     if (need && (ranges_overlap(ws, need, x, bytes) || ranges_overlap(ws, need, b, bytes)))
         return set_error(MRHS_EINVAL, "workspace overlaps a vector");
-    return launch_sap(op, b, x, n_rhs, n_sap, n_mr, ws, (hipStream_t)stream);
+    return launch_sap(op, b, x, n_rhs, n_sap, n_mr, ws, (hipStream_t)stream, guess);
+}
+
+}  // namespace
+
+int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    return sap_common(op, b, x, n_rhs, n_sap, n_mr, ws, ws_bytes, stream, false);
+}
+
+int sap_smooth_mrhs_guess(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
+                          void *ws, size_t ws_bytes, void *stream)
+{
+    return sap_common(op, b, x, n_rhs, n_sap, n_mr, ws, ws_bytes, stream, true);
 }
 
 int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out, void *ws,
@@ -361,6 +377,67 @@ int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n
     (void)ws;
     (void)ws_bytes;
     return launch_coarse(op, Q, q_dtype, n_tv, Dc, (hipStream_t)stream);
+}
+
+size_t mrhs_coarse_vector_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs)
+{
+    if (!op || n_tv <= 0 || n_rhs <= 0) return 0;
+    return (size_t)op->n_agg * 2 * n_tv * 2 * ((n_rhs + 3) / 4 * 4) * sizeof(float);
+}
+
+namespace {
+
+int check_transfer(const mrhs_op *op, int n_tv, int n_rhs, int q_dtype)
+{
+    if (int rc = check_op(op)) return rc;
+    if (int rc = check_nrhs(n_tv)) return rc;
+    if (int rc = check_nrhs(n_rhs)) return rc;
+    if (n_tv > 32 || n_rhs > 32) return set_error(MRHS_EUNSUPPORTED, "at most 32 test vectors and 32 right-hand sides");
+    if (n_tv > 6 * op->Va) return set_error(MRHS_EINVAL, "more test vectors than rows of an aggregate half");
+    if (q_dtype != MRHS_DTYPE_F32 && q_dtype != MRHS_DTYPE_F64)
+        return set_error(MRHS_EUNSUPPORTED, "test vectors must be FP32 or FP64");
+    if (transfer_lds_bytes(op) > op->max_lds) return set_error(MRHS_EUNSUPPORTED, "aggregate too large for the LDS");
+    return MRHS_OK;
+}
+
+}  // namespace
+
+int restrict_mrhs(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, const void *y, int32_t y_dtype,
+                  float *yc, int32_t n_rhs, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, q_dtype)) return rc;
+    if (int rc = check_dtype(y_dtype)) return rc;
+    if (!Q || !y || !yc) return set_error(MRHS_EINVAL, "null argument");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    if (ranges_overlap(yc, cb, y, native_elems(op, n_rhs) * dtype_size(y_dtype)) ||
+        ranges_overlap(yc, cb, Q, native_elems(op, n_tv) * dtype_size(q_dtype)))
+        return set_error(MRHS_EINVAL, "coarse output overlaps an input");
+    return launch_restrict(op, Q, q_dtype, n_tv, y, y_dtype, yc, n_rhs, (hipStream_t)stream);
+}
+
+int prolong_mrhs(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, const float *yc, void *y,
+                 int32_t y_dtype, int32_t n_rhs, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, q_dtype)) return rc;
+    if (int rc = check_dtype(y_dtype)) return rc;
+    if (!Q || !y || !yc) return set_error(MRHS_EINVAL, "null argument");
+    const size_t yb = native_elems(op, n_rhs) * dtype_size(y_dtype);
+    if (ranges_overlap(y, yb, yc, mrhs_coarse_vector_bytes(op, n_tv, n_rhs)) ||
+        ranges_overlap(y, yb, Q, native_elems(op, n_tv) * dtype_size(q_dtype)))
+        return set_error(MRHS_EINVAL, "fine output overlaps an input");
+    return launch_prolong(op, Q, q_dtype, n_tv, yc, y, y_dtype, n_rhs, (hipStream_t)stream);
+}
+
+int coarse_apply_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const float *yc, float *yc_out,
+                      int32_t n_rhs, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, MRHS_DTYPE_F32)) return rc;
+    if (!Dc || !yc || !yc_out) return set_error(MRHS_EINVAL, "null argument");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    if (ranges_overlap(yc_out, cb, yc, cb) ||
+        ranges_overlap(yc_out, cb, Dc, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(float)))
+        return set_error(MRHS_EINVAL, "coarse output overlaps an input");
+    return launch_coarse_apply(op, Dc, n_tv, yc, yc_out, n_rhs, (hipStream_t)stream);
 }
 
 size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const int32_t *n_rhs)

@@ -67,6 +67,11 @@ template <typename Tc, typename Ts> __device__ inline Tc load_as(const Ts *p) { 
 template <> __device__ inline float load_as<float, __half>(const __half *p) { return __half2float(*p); }
 template <> __device__ inline double load_as<double, __half>(const __half *p) { return (double)__half2float(*p); }
 
+// type in which a neighbour spinor of storage type Ts is held for arithmetic in Tc
+template <typename Tc, typename Ts> struct ChiType { using type = Tc; };
+template <> struct ChiType<double, float> { using type = float; };
+template <> struct ChiType<double, __half> { using type = float; };
+
 template <typename Ts, typename Tc> __device__ inline Ts store_as(Tc v) { return static_cast<Ts>(v); }
 template <> __device__ inline __half store_as<__half, float>(float v) { return __float2half_rn(v); }
 // double -> binary16 with a single round-to-nearest-even
@@ -109,8 +114,10 @@ template <int P, typename T> __device__ inline void mul_ipow(T re, T im, T &ore,
 // W = U (DAG = false) or U^dag (DAG = true), U given as 18 reals (row-major re, im).
 // The spin projector has rank 2: project to a half spinor, multiply two colour vectors,
 // then rebuild the lower two spin rows from the upper two.
-template <int MU, int SGN, bool DAG, typename T>
-__device__ inline void hop_accumulate(const T (&U)[18], const Spinor<T> &chi, Spinor<T> &acc)
+// chi may be held in a narrower type than the arithmetic (FP32 or FP16 storage read by the
+// FP64 residual): its entries are converted (exactly) where they are used.
+template <int MU, int SGN, bool DAG, typename T, typename Tx>
+__device__ inline void hop_accumulate(const T (&U)[18], const Spinor<Tx> &chi, Spinor<T> &acc)
 {
     constexpr int s = SGN > 0 ? 0 : 2;  // phase exponent of the sign
     T hre[2][3], him[2][3];
@@ -120,18 +127,20 @@ __device__ inline void hop_accumulate(const T (&U)[18], const Spinor<T> &chi, Sp
         for (int c = 0; c < 3; ++c) {
             T are, aim;
             if (r == 0)
-                mul_ipow<gphase(MU, 0) + s>(chi.re[3 * gperm(MU, 0) + c], chi.im[3 * gperm(MU, 0) + c], are, aim);
+                mul_ipow<gphase(MU, 0) + s>(T(chi.re[3 * gperm(MU, 0) + c]), T(chi.im[3 * gperm(MU, 0) + c]), are, aim);
             else
-                mul_ipow<gphase(MU, 1) + s>(chi.re[3 * gperm(MU, 1) + c], chi.im[3 * gperm(MU, 1) + c], are, aim);
-            hre[r][c] = chi.re[3 * r + c] + are;
-            him[r][c] = chi.im[3 * r + c] + aim;
+                mul_ipow<gphase(MU, 1) + s>(T(chi.re[3 * gperm(MU, 1) + c]), T(chi.im[3 * gperm(MU, 1) + c]), are, aim);
+            hre[r][c] = T(chi.re[3 * r + c]) + are;
+            him[r][c] = T(chi.im[3 * r + c]) + aim;
         }
     }
-    T wre[2][3], wim[2][3];
+    // colour row a of W h for both half-spinor rows, added to all four spin rows at once, so
+    // that only one colour row of the product is live at a time
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int a = 0; a < 3; ++a) {
+        T wre[2], wim[2];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+        for (int r = 0; r < 2; ++r) {
             T sr = 0, si = 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -144,19 +153,17 @@ __device__ inline void hop_accumulate(const T (&U)[18], const Spinor<T> &chi, Sp
                 si += ur * him[r][c];
                 si += ui * hre[r][c];
             }
-            wre[r][a] = sr;
-            wim[r][a] = si;
+            wre[r] = sr;
+            wim[r] = si;
         }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc.re[a] += wre[0][a];
-        acc.im[a] += wim[0][a];
-        acc.re[3 + a] += wre[1][a];
-        acc.im[3 + a] += wim[1][a];
+        acc.re[a] += wre[0];
+        acc.im[a] += wim[0];
+        acc.re[3 + a] += wre[1];
+        acc.im[3 + a] += wim[1];
         T t2r, t2i, t3r, t3i;
         // row 2 = (SGN phase of row 2) * h[perm(2)], row 3 likewise
-        mul_ipow<gphase(MU, 2) + s>(wre[gperm(MU, 2)][a], wim[gperm(MU, 2)][a], t2r, t2i);
-        mul_ipow<gphase(MU, 3) + s>(wre[gperm(MU, 3)][a], wim[gperm(MU, 3)][a], t3r, t3i);
+        mul_ipow<gphase(MU, 2) + s>(wre[gperm(MU, 2)], wim[gperm(MU, 2)], t2r, t2i);
+        mul_ipow<gphase(MU, 3) + s>(wre[gperm(MU, 3)], wim[gperm(MU, 3)], t3r, t3i);
         acc.re[6 + a] += t2r;
         acc.im[6 + a] += t2i;
         acc.re[9 + a] += t3r;
@@ -167,12 +174,13 @@ __device__ inline void hop_accumulate(const T (&U)[18], const Spinor<T> &chi, Sp
 // out[6hf..6hf+5] = A_hf psi[6hf..6hf+5] for one chiral half hf of the site term, held
 // as 36 reals: 6 real diagonal entries, then the 15 upper entries (i<j, row-major) as
 // (re, im); the lower triangle is their conjugate.
-template <int HF, typename T> __device__ inline void clover_half(const T (&cl)[36], const Spinor<T> &psi, Spinor<T> &out)
+template <int HF, typename T, typename Tx>
+__device__ inline void clover_half(const T (&cl)[36], const Spinor<Tx> &psi, Spinor<T> &out)
 {
     constexpr int o = 6 * HF;
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        T sr = cl[i] * psi.re[o + i], si = cl[i] * psi.im[o + i];
+        T sr = cl[i] * T(psi.re[o + i]), si = cl[i] * T(psi.im[o + i]);
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
             if (j == i) continue;
@@ -180,10 +188,10 @@ template <int HF, typename T> __device__ inline void clover_half(const T (&cl)[3
             const int kidx = a * 5 - a * (a - 1) / 2 + (bb - a - 1);  // index of pair (a,bb), a<bb
             T ur = cl[6 + 2 * kidx], ui = cl[7 + 2 * kidx];
             if (i > j) ui = -ui;  // lower triangle: conjugate
-            sr += ur * psi.re[o + j];
-            sr -= ui * psi.im[o + j];
-            si += ur * psi.im[o + j];
-            si += ui * psi.re[o + j];
+            sr += ur * T(psi.re[o + j]);
+            sr -= ui * T(psi.im[o + j]);
+            si += ur * T(psi.im[o + j]);
+            si += ui * T(psi.re[o + j]);
         }
         out.re[o + i] = sr;
         out.im[o + i] = si;
@@ -271,7 +279,8 @@ int launch_build_fields(mrhs_op *op, const double *links_canon, double m0, doubl
 int launch_pack(const mrhs_op *op, const double *canon, void *native, int dtype, int n_rhs, int *flag, hipStream_t st);
 int launch_unpack(const mrhs_op *op, const void *native, int dtype, double *canon, int n_rhs, hipStream_t st);
 int launch_dirac(const mrhs_op *op, const void *x, void *y, int n_rhs, hipStream_t st);
-int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st);
+int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st,
+               bool guess = false);
 int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st);
 int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *ws,
               hipStream_t st);
@@ -279,9 +288,16 @@ int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc,
 size_t ws_bytes_sap(const mrhs_op *op, int n_rhs);
 size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs);
 int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
-                       int n_sap, int n_mr, void *ws, hipStream_t st);
+                       int n_sap, int n_mr, void *ws, hipStream_t st, bool guess = false);
 size_t ws_bytes_residual(const mrhs_op *op, int n_rhs);
 size_t ws_bytes_gs(const mrhs_op *op, int n_tv);
 size_t ws_bytes_coarse(const mrhs_op *op, int n_tv);
 size_t native_elems(const mrhs_op *op, int n_rhs);
 int dtype_size(int dtype);
+int launch_restrict(const mrhs_op *op, const void *Q, int qdt, int n_tv, const void *y, int ydt, float *yc, int n,
+                    hipStream_t st);
+int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const float *yc, void *y, int ydt, int n,
+                   hipStream_t st);
+int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,
+                        hipStream_t st);
+size_t transfer_lds_bytes(const mrhs_op *op);

@@ -290,7 +290,7 @@ int launch_batched(const SapBatch<Ts, Tc> &B, int threads, size_t lds, hipStream
 
 template <typename Ts, typename Tc>
 int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
-                         int n_sap, int n_mr, char *ws, hipStream_t st)
+                         int n_sap, int n_mr, char *ws, bool guess, hipStream_t st)
 {
     // one tile for the whole batch: the smallest of the operators' tiles (all divide S)
     int T = 4, maxVb = 0;
@@ -303,6 +303,7 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
     const size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + (size_t)(threads / 64) * T * 3);
     if (maxVb * T > 1024 || lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "batched SAP tile does not fit");
     if (n_sap == 0) {
+        if (guess) return MRHS_OK;  // no sweep: x keeps the starting guess
         for (int k = 0; k < n; ++k) {
             hipLaunchKernelGGL(k_fill_zero<Ts>, dim3(1024), dim3(256), 0, st, (Ts *)x[k], (long)native_elems(ops[k], n_rhs[k]));
             if (int rc = hip_check(hipGetLastError(), "k_fill_zero launch")) return rc;
@@ -341,7 +342,7 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
                 a.colour = c;
                 a.blocks = op->colour_blocks + (c == 0 ? 0 : op->n_colour[0]);
                 a.nblocks = op->n_colour[c];
-                a.mode = s == 0 ? c : 2;
+                a.mode = s == 0 && !guess ? c : 2;  // from zero, x vanishes on blocks not yet visited
                 a.xr = a.x;
                 if (a.mode == 2 && op->odd_blocks) {
                     C.src[C.n_inst] = a.x;
@@ -380,22 +381,23 @@ size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_r
 }
 
 int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
-                       int n_sap, int n_mr, void *ws, hipStream_t st)
+                       int n_sap, int n_mr, void *ws, hipStream_t st, bool guess)
 {
     if (n > MAX_BATCH) return set_error(MRHS_EUNSUPPORTED, "more than 8 operators in one batch");
     switch (ops[0]->prec) {
     case MRHS_PREC_F64:
-        return sap_batched_dispatch<double, double>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+        return sap_batched_dispatch<double, double>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, guess, st);
     case MRHS_PREC_F32:
-        return sap_batched_dispatch<float, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+        return sap_batched_dispatch<float, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, guess, st);
     default:
-        return sap_batched_dispatch<__half, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, st);
+        return sap_batched_dispatch<__half, float>(ops, n, b, x, n_rhs, n_sap, n_mr, (char *)ws, guess, st);
     }
 }
 
 size_t ws_bytes_sap(const mrhs_op *op, int n_rhs) { return ws_bytes_sap_batched(&op, 1, &n_rhs); }
 
-int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st)
+int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st,
+               bool guess)
 {
-    return launch_sap_batched(&op, 1, &b, &x, &n_rhs, n_sap, n_mr, ws, st);
+    return launch_sap_batched(&op, 1, &b, &x, &n_rhs, n_sap, n_mr, ws, st, guess);
 }

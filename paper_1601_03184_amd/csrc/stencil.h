@@ -105,8 +105,8 @@ __device__ inline int block_colour(const KGeo &g, const uint32_t *__restrict__ b
 }
 
 // out = A(x) psi, one chiral half at a time (36 field values live, not 72)
-template <typename Tf, typename Tc>
-__device__ inline void clover_site(const Tf *__restrict__ clover, long V, long site, const Spinor<Tc> &psi, Spinor<Tc> &out)
+template <typename Tf, typename Tc, typename Tx>
+__device__ inline void clover_site(const Tf *__restrict__ clover, long V, long site, const Spinor<Tx> &psi, Spinor<Tc> &out)
 {
     {
         Tc A[36];
@@ -133,8 +133,8 @@ __device__ inline void hop_pair_global(const KGeo &g, const Tf *__restrict__ lin
     {
         const NbrSite n = nbr_fwd(g, MU, blk, off, bc, lc);
         if (!skip(n.blk)) {
-            Spinor<Tc> chi;
-            load_spinor<Tc>(g, x, grp, n.blk, n.off, t, chi);
+            Spinor<typename ChiType<Tc, Ts>::type> chi;
+            load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
             Tc U[18];
             load_link(links, g.V, MU, ns, U);
             hop_accumulate<MU, -1, false>(U, chi, out);
@@ -144,8 +144,8 @@ __device__ inline void hop_pair_global(const KGeo &g, const Tf *__restrict__ lin
     {
         const NbrSite n = nbr_bwd(g, MU, blk, off, bc, lc);
         if (!skip(n.blk)) {
-            Spinor<Tc> chi;
-            load_spinor<Tc>(g, x, grp, n.blk, n.off, t, chi);
+            Spinor<typename ChiType<Tc, Ts>::type> chi;
+            load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
             Tc U[18];
             load_link(links, g.V, MU, (long)n.blk * g.Vb + n.off, U);
             hop_accumulate<MU, +1, true>(U, chi, out);
@@ -160,8 +160,8 @@ __device__ inline void dirac_site_global(const KGeo &g, const Tf *__restrict__ l
                                          const int (&lc)[4], Spinor<Tc> &out, Skip skip)
 {
     if (!skip(blk)) {
-        Spinor<Tc> own;
-        load_spinor<Tc>(g, x, grp, blk, off, t, own);
+        Spinor<typename ChiType<Tc, Ts>::type> own;
+        load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, blk, off, t, own);
         clover_site(clover, g.V, (long)blk * g.Vb + off, own, out);
     } else {
         spinor_zero(out);

@@ -1,0 +1,393 @@
+// transfer.hip -- the coarse-grid correction's building blocks on all right-hand sides at
+// once (the refinement phase of the setup, Alg. 1 and 2): restriction y_c = R y and
+// prolongation y = P y_c with R = Q^dag, P = Q per aggregate and spin half (Alg. 3), and the
+// coarse operator applied to coarse vectors (the operator of the coarse solve).
+//
+// With the right-hand sides innermost each of these is a matrix-matrix product (Sec. 6):
+//   restriction : (y_c)^h_i [N x n]      = (Q^h_i)^dag [N x 6Va] . y^h_i [6Va x n]
+//   prolongation: y^h_i     [6Va x n]    = Q^h_i [6Va x N]       . (y_c)^h_i [N x n]
+//   coarse apply: (D_c y_c)(i) [2N x n]  = sum_d Dc[i][d] [2N x 2N] . y_c(nbr_d(i)) [2N x n]
+// and runs on v_mfma_f32_16x16x4f32 (complex = 4 real products) with FP32 accumulation.
+// Lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds D[4(l/16) + r][l%16] in
+// accumulator register r.
+//
+// Coarse vectors (FP32): element (rhs k, coarse site i, coarse dof c = h n_tv + j, re/im p)
+// at ((i * 2 n_tv + c) * 2 + p) * ldc + k, ldc = n rounded up to a multiple of 4.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
+
+constexpr int TTHR = 256;  // 4 wavefronts
+constexpr int TNW = TTHR / 64;
+
+template <typename T> __device__ inline float to_f32(T v) { return (float)v; }
+template <> __device__ inline float to_f32<__half>(__half v) { return __half2float(v); }
+
+struct TransArgs {
+    KGeo g;
+    int Va, n_agg, N, n, ldc;
+    const int32_t *agg_sites;
+    const void *Q;  // native test vectors (N of them)
+    const void *y;  // native fine vectors (n of them)
+    void *yo;       // native fine output (prolongation)
+    const float *yc;
+    float *yco;
+};
+
+// native element offset (without the vector part) of row r of half h of an aggregate, the
+// aggregate's site offsets staged in sbase
+__device__ inline uint32_t trow_off(const uint32_t *sbase, int h, uint32_t cstr, int r)
+{
+    const int sl = r / 6, q = r - 6 * sl;
+    const int sp = q >= 3 ? 1 : 0, c = q - 3 * sp;
+    return sbase[sl] + (uint32_t)(2 * (3 * (2 * h + sp) + c)) * cstr;
+}
+
+// vector k of a native set: group and lane part of the element offset
+__device__ inline size_t tcol_off(const KGeo &g, int k)
+{
+    const int grp = k / g.S, t = k - grp * g.S;
+    return (size_t)grp * g.nblk * 24 * g.Vb * g.S + t;
+}
+
+__device__ inline void stage_agg_sites(const TransArgs &a, int i, uint32_t *sbase)
+{
+    for (int s = threadIdx.x; s < a.Va; s += blockDim.x) {
+        const int ns = a.agg_sites[(size_t)i * a.Va + s];
+        const int blk = ns / a.g.Vb, off = ns - blk * a.g.Vb;
+        sbase[s] = ((uint32_t)blk * 24u * (uint32_t)a.g.Vb + (uint32_t)off) * (uint32_t)a.g.S;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// restriction: one workgroup per (aggregate i, half h).  Output tiles: rows j (test
+// vectors), columns k (right-hand sides), at most 2 x 2.  The wavefronts split the 6Va rows
+// (K) and their partial tiles are summed in LDS in a fixed order.
+// ---------------------------------------------------------------------------------------
+template <typename Tq, typename Ty>
+__global__ void __launch_bounds__(TTHR) k_restrict(TransArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *sbase = reinterpret_cast<uint32_t *>(smem);          // [Va]
+    float *part = reinterpret_cast<float *>(sbase + a.Va);          // [2 (re/im)][32][32]
+    const int i = blockIdx.x >> 1, h = blockIdx.x & 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Tq *Q = static_cast<const Tq *>(a.Q);
+    const Ty *y = static_cast<const Ty *>(a.y);
+    const uint32_t cstr = (uint32_t)a.g.Vb * (uint32_t)a.g.S;
+    const int TJ = (a.N + 15) / 16, TK = (a.n + 15) / 16;
+    stage_agg_sites(a, i, sbase);
+
+    f4 ar[2][2], ai[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int z = 0; z < 2; ++z) ar[x][z] = ai[x][z] = f4{0.f, 0.f, 0.f, 0.f};
+    // per lane: test vector j = 16 tj + l%16 (A operand column), rhs k = 16 tk + l%16
+    size_t qo[2], yo[2];
+    bool qok[2], yok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int j = 16 * t + (lane & 15);
+        qok[t] = t < TJ && j < a.N;
+        qo[t] = qok[t] ? tcol_off(a.g, j) : 0;
+        yok[t] = t < TK && j < a.n;
+        yo[t] = yok[t] ? tcol_off(a.g, j) : 0;
+    }
+    const int rows = 6 * a.Va;
+    for (int r0 = 4 * wave; r0 < rows; r0 += 4 * TNW) {
+        const int r = r0 + (lane >> 4);
+        const bool rok = r < rows;
+        const uint32_t ro = rok ? trow_off(sbase, h, cstr, r) : 0;
+        float qr[2], qi[2], yr[2], yi[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const bool okq = rok && qok[t], oky = rok && yok[t];
+            const size_t iq = okq ? ro + qo[t] : 0, iy = oky ? ro + yo[t] : 0;
+            const float a0 = to_f32(Q[iq]), a1 = to_f32(Q[okq ? iq + cstr : 0]);
+            const float b0 = to_f32(y[iy]), b1 = to_f32(y[oky ? iy + cstr : 0]);
+            qr[t] = okq ? a0 : 0.f;
+            qi[t] = okq ? a1 : 0.f;
+            yr[t] = oky ? b0 : 0.f;
+            yi[t] = oky ? b1 : 0.f;
+        }
+        // conj(q) y = (qr yr + qi yi) + i (qr yi - qi yr)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int tk = 0; tk < 2; ++tk) {
+                if (tj >= TJ || tk >= TK) continue;
+                ar[tj][tk] = mfma32(qr[tj], yr[tk], ar[tj][tk]);
+                ar[tj][tk] = mfma32(qi[tj], yi[tk], ar[tj][tk]);
+                ai[tj][tk] = mfma32(qr[tj], yi[tk], ai[tj][tk]);
+                ai[tj][tk] = mfma32(-qi[tj], yr[tk], ai[tj][tk]);
+            }
+    }
+    // partial tiles of the wavefronts summed in order
+    for (int w = 0; w < TNW; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int tk = 0; tk < 2; ++tk) {
+                    if (tj >= TJ || tk >= TK) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = 16 * tj + 4 * (lane >> 4) + q, k = 16 * tk + (lane & 15);
+                        float *pr = part + j * 32 + k, *pi = part + 1024 + j * 32 + k;
+                        *pr = w == 0 ? ar[tj][tk][q] : *pr + ar[tj][tk][q];
+                        *pi = w == 0 ? ai[tj][tk][q] : *pi + ai[tj][tk][q];
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    // (y_c)^h_i: dof c = h N + j, right-hand side k (padding columns written as zero)
+    float *out = a.yco + ((size_t)i * 2 * a.N + h * a.N) * 2 * a.ldc;
+    for (int e = threadIdx.x; e < a.N * a.ldc; e += blockDim.x) {
+        const int j = e / a.ldc, k = e - j * a.ldc;
+        const bool ok = k < a.n;
+        out[(size_t)(2 * j) * a.ldc + k] = ok ? part[j * 32 + k] : 0.f;
+        out[(size_t)(2 * j + 1) * a.ldc + k] = ok ? part[1024 + j * 32 + k] : 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// prolongation: one workgroup per (aggregate i, half h).  (y_c)^h_i is staged in LDS; each
+// wavefront forms 16-row blocks of Q^h_i (y_c)^h_i, K = the test vectors.
+// ---------------------------------------------------------------------------------------
+template <typename Tq, typename Ty>
+__global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *sbase = reinterpret_cast<uint32_t *>(smem);  // [Va]
+    float *ycs = reinterpret_cast<float *>(sbase + a.Va);   // [2 (re/im)][32 (j)][32 (k)]
+    const int i = blockIdx.x >> 1, h = blockIdx.x & 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Tq *Q = static_cast<const Tq *>(a.Q);
+    Ty *yo = static_cast<Ty *>(a.yo);
+    const uint32_t cstr = (uint32_t)a.g.Vb * (uint32_t)a.g.S;
+    const int TK = (a.n + 15) / 16, KS = (a.N + 3) / 4;
+    for (int e = threadIdx.x; e < 2048; e += blockDim.x) {
+        const int p = e >> 10, j = (e >> 5) & 31, k = e & 31;
+        float v = 0.f;
+        if (j < a.N && k < a.n) v = a.yc[(((size_t)i * 2 * a.N + h * a.N + j) * 2 + p) * a.ldc + k];
+        ycs[e] = v;
+    }
+    stage_agg_sites(a, i, sbase);
+    // output lanes: the n right-hand sides and the padding lanes of the last group (zero)
+    const int nw = (a.n + a.g.S - 1) / a.g.S * a.g.S;
+    size_t yoff[2];
+    bool kok[2], kin[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int k = 16 * t + (lane & 15);
+        kok[t] = t < TK && k < nw;
+        kin[t] = k < a.n;
+        yoff[t] = kok[t] ? tcol_off(a.g, k) : 0;
+    }
+    const int rows = 6 * a.Va;
+    for (int b0 = 16 * wave; b0 < rows; b0 += 16 * TNW) {
+        const int ra = b0 + (lane & 15);  // A operand row
+        const bool raok = ra < rows;
+        const uint32_t roa = raok ? trow_off(sbase, h, cstr, ra) : 0;
+        f4 dr[2], di[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) dr[t] = di[t] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < KS; ++ks) {
+            const int j = 4 * ks + (lane >> 4);  // K index: test vector
+            const bool ok = raok && j < a.N;
+            const size_t iq = ok ? roa + tcol_off(a.g, j) : 0;
+            const float q0 = to_f32(Q[iq]), q1 = to_f32(Q[ok ? iq + cstr : 0]);
+            const float qr = ok ? q0 : 0.f, qi = ok ? q1 : 0.f;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (t >= TK) continue;
+                const int k = 16 * t + (lane & 15);
+                const float br = ycs[j * 32 + k], bi = ycs[1024 + j * 32 + k];  // j < 32 always
+                // q y_c = (qr br - qi bi) + i (qr bi + qi br)
+                dr[t] = mfma32(qr, br, dr[t]);
+                dr[t] = mfma32(-qi, bi, dr[t]);
+                di[t] = mfma32(qr, bi, di[t]);
+                di[t] = mfma32(qi, br, di[t]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = b0 + 4 * (lane >> 4) + q;
+            if (r >= rows) continue;
+            const uint32_t ro = trow_off(sbase, h, cstr, r);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (!kok[t]) continue;
+                const size_t idx = ro + yoff[t];
+                yo[idx] = store_as<Ty>(kin[t] ? dr[t][q] : 0.f);
+                yo[idx + cstr] = store_as<Ty>(kin[t] ? di[t][q] : 0.f);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// coarse apply: one workgroup per coarse site.  Output tiles: rows (2N dofs) x columns
+// (right-hand sides), at most 4 x 2, two per wavefront; K runs over the 9 blocks and their
+// 2N columns.
+// ---------------------------------------------------------------------------------------
+struct CApplyArgs {
+    int na[4];
+    int Vc, N, n, ldc;
+    const float *Dc;  // [Vc][9][2N][2N][2]
+    const float *yc;
+    float *yco;
+};
+
+__global__ void __launch_bounds__(TTHR) k_coarse_apply(CApplyArgs a)
+{
+    const int i = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int N2 = 2 * a.N;
+    const int TR = (N2 + 15) / 16, TK = (a.n + 15) / 16, ntile = TR * TK, KS = (N2 + 3) / 4;
+    int c[4], r = i;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        c[m] = r % a.na[m];
+        r /= a.na[m];
+    }
+    f4 dr[2], di[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) dr[m] = di[m] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int d = 0; d < 9; ++d) {
+        int cn[4] = {c[0], c[1], c[2], c[3]};
+        if (d >= 1 && d <= 4) cn[d - 1] = (cn[d - 1] + 1) % a.na[d - 1];
+        if (d >= 5) cn[d - 5] = (cn[d - 5] - 1 + a.na[d - 5]) % a.na[d - 5];
+        const int j = cn[0] + a.na[0] * (cn[1] + a.na[1] * (cn[2] + a.na[2] * cn[3]));
+        const float *blk = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
+        const float *yj = a.yc + (size_t)j * N2 * 2 * a.ldc;
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const int tile = wave + TNW * m;
+            if (tile >= ntile) break;
+            const int tr = tile / TK, tk = tile - tr * TK;
+            const int row = 16 * tr + (lane & 15), k = 16 * tk + (lane & 15);
+            const bool rok = row < N2, kok = k < a.n;
+            for (int ks = 0; ks < KS; ++ks) {
+                const int col = 4 * ks + (lane >> 4);  // K index: the block's column (coarse dof)
+                const bool aok = rok && col < N2, bok = kok && col < N2;
+                const size_t ia = aok ? ((size_t)row * N2 + col) * 2 : 0;
+                const size_t ib = bok ? (size_t)(2 * col) * a.ldc + k : 0;
+                const float a0 = blk[ia], a1 = blk[aok ? ia + 1 : 0];
+                const float b0 = yj[ib], b1 = yj[bok ? ib + a.ldc : 0];
+                const float xr = aok ? a0 : 0.f, xi = aok ? a1 : 0.f;
+                const float yr = bok ? b0 : 0.f, yi = bok ? b1 : 0.f;
+                // D y = (xr yr - xi yi) + i (xr yi + xi yr)
+                dr[m] = mfma32(xr, yr, dr[m]);
+                dr[m] = mfma32(-xi, yi, dr[m]);
+                di[m] = mfma32(xr, yi, di[m]);
+                di[m] = mfma32(xi, yr, di[m]);
+            }
+        }
+    }
+    float *out = a.yco + (size_t)i * N2 * 2 * a.ldc;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int tile = wave + TNW * m;
+        if (tile >= ntile) break;
+        const int tr = tile / TK, tk = tile - tr * TK;
+        const int k = 16 * tk + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = 16 * tr + 4 * (lane >> 4) + q;
+            if (row < N2 && k < a.ldc) {
+                out[(size_t)(2 * row) * a.ldc + k] = k < a.n ? dr[m][q] : 0.f;
+                out[(size_t)(2 * row + 1) * a.ldc + k] = k < a.n ? di[m][q] : 0.f;
+            }
+        }
+    }
+}
+
+TransArgs trans_args(const mrhs_op *op, int n_tv, int n)
+{
+    TransArgs a{};
+    a.g = op->k;
+    a.Va = op->Va;
+    a.n_agg = op->n_agg;
+    a.N = n_tv;
+    a.n = n;
+    a.ldc = (n + 3) / 4 * 4;
+    a.agg_sites = op->agg_sites;
+    return a;
+}
+
+template <typename Tq, typename Ty> int restrict_typed(const TransArgs &a, hipStream_t st)
+{
+    const size_t lds = sizeof(uint32_t) * a.Va + sizeof(float) * 2048;
+    hipLaunchKernelGGL((k_restrict<Tq, Ty>), dim3(2 * a.n_agg), dim3(TTHR), lds, st, a);
+    return hip_check(hipGetLastError(), "k_restrict launch");
+}
+
+template <typename Tq, typename Ty> int prolong_typed(const TransArgs &a, hipStream_t st)
+{
+    const size_t lds = sizeof(uint32_t) * a.Va + sizeof(float) * 2048;
+    hipLaunchKernelGGL((k_prolong<Tq, Ty>), dim3(2 * a.n_agg), dim3(TTHR), lds, st, a);
+    return hip_check(hipGetLastError(), "k_prolong launch");
+}
+
+template <typename Tq> int restrict_y(const TransArgs &a, int ydt, hipStream_t st)
+{
+    if (ydt == MRHS_DTYPE_F64) return restrict_typed<Tq, double>(a, st);
+    if (ydt == MRHS_DTYPE_F32) return restrict_typed<Tq, float>(a, st);
+    return restrict_typed<Tq, __half>(a, st);
+}
+
+template <typename Tq> int prolong_y(const TransArgs &a, int ydt, hipStream_t st)
+{
+    if (ydt == MRHS_DTYPE_F64) return prolong_typed<Tq, double>(a, st);
+    if (ydt == MRHS_DTYPE_F32) return prolong_typed<Tq, float>(a, st);
+    return prolong_typed<Tq, __half>(a, st);
+}
+
+}  // namespace
+
+size_t transfer_lds_bytes(const mrhs_op *op) { return sizeof(uint32_t) * op->Va + sizeof(float) * 2048; }
+
+int launch_restrict(const mrhs_op *op, const void *Q, int qdt, int n_tv, const void *y, int ydt, float *yc, int n,
+                    hipStream_t st)
+{
+    TransArgs a = trans_args(op, n_tv, n);
+    a.Q = Q;
+    a.y = y;
+    a.yco = yc;
+    return qdt == MRHS_DTYPE_F64 ? restrict_y<double>(a, ydt, st) : restrict_y<float>(a, ydt, st);
+}
+
+int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const float *yc, void *y, int ydt, int n,
+                   hipStream_t st)
+{
+    TransArgs a = trans_args(op, n_tv, n);
+    a.Q = Q;
+    a.yc = yc;
+    a.yo = y;
+    return qdt == MRHS_DTYPE_F64 ? prolong_y<double>(a, ydt, st) : prolong_y<float>(a, ydt, st);
+}
+
+int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,
+                        hipStream_t st)
+{
+    CApplyArgs a{};
+    for (int mu = 0; mu < 4; ++mu) a.na[mu] = op->na[mu];
+    a.Vc = op->n_agg;
+    a.N = n_tv;
+    a.n = n;
+    a.ldc = (n + 3) / 4 * 4;
+    a.Dc = Dc;
+    a.yc = yc;
+    a.yco = yco;
+    hipLaunchKernelGGL(k_coarse_apply, dim3(a.Vc), dim3(TTHR), 0, st, a);
+    return hip_check(hipGetLastError(), "k_coarse_apply launch");
+}

@@ -51,12 +51,17 @@ def lib():
             "mrhs_unpack": (i32, [p, p, i32, p, i32, p]),
             "dirac_apply_mrhs": (i32, [p, p, p, i32, p]),
             "sap_smooth_mrhs": (i32, [p, p, p, i32, i32, i32, p, sz, p]),
+            "sap_smooth_mrhs_guess": (i32, [p, p, p, i32, i32, i32, p, sz, p]),
             "mrhs_residual_norms": (i32, [p, p, p, i32, p, p, sz, p]),
             "block_orthonormalize": (i32, [p, p, i32, p, i32, i32, p, p, sz, p]),
             "coarse_op_build": (i32, [p, p, i32, i32, p, p, sz, p]),
             "mrhs_set_tiles": (i32, [p, i32, i32]),
             "sap_smooth_mrhs_batched": (i32, [p, i32, p, p, p, i32, i32, p, sz, p]),
             "mrhs_batched_workspace_bytes": (sz, [p, i32, p]),
+            "mrhs_coarse_vector_bytes": (sz, [p, i32, i32]),
+            "restrict_mrhs": (i32, [p, p, i32, i32, p, i32, p, i32, p]),
+            "prolong_mrhs": (i32, [p, p, i32, i32, p, p, i32, i32, p]),
+            "coarse_apply_mrhs": (i32, [p, p, i32, p, p, i32, p]),
             "mrhs_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -139,6 +144,12 @@ def sap_smooth_mrhs(op, b, x, n_rhs, n_sap, n_mr, ws, stream=None):
                                  _stream(stream)))
 
 
+def sap_smooth_mrhs_guess(op, b, x, n_rhs, n_sap, n_mr, ws, stream=None):
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().sap_smooth_mrhs_guess(op, _dptr(b), _dptr(x), int(n_rhs), int(n_sap), int(n_mr), _dptr(ws), nb,
+                                       _stream(stream)))
+
+
 def mrhs_residual_norms(op, b, x, n_rhs, out, ws, stream=None):
     _check(lib().mrhs_residual_norms(op, _dptr(b), _dptr(x), int(n_rhs), _dptr(out), _dptr(ws),
                                      ws.numel() * ws.element_size(), _stream(stream)))
@@ -153,6 +164,24 @@ def block_orthonormalize(op, V, v_dtype, Q, q_dtype, n_tv, status, ws, stream=No
 def coarse_op_build(op, Q, q_dtype, n_tv, Dc, ws, stream=None):
     nb = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().coarse_op_build(op, _dptr(Q), int(q_dtype), int(n_tv), _dptr(Dc), _dptr(ws), nb, _stream(stream)))
+
+
+def mrhs_coarse_vector_bytes(op, n_tv, n_rhs):
+    return lib().mrhs_coarse_vector_bytes(op, int(n_tv), int(n_rhs))
+
+
+def restrict_mrhs(op, Q, q_dtype, n_tv, y, y_dtype, yc, n_rhs, stream=None):
+    _check(lib().restrict_mrhs(op, _dptr(Q), int(q_dtype), int(n_tv), _dptr(y), int(y_dtype), _dptr(yc), int(n_rhs),
+                               _stream(stream)))
+
+
+def prolong_mrhs(op, Q, q_dtype, n_tv, yc, y, y_dtype, n_rhs, stream=None):
+    _check(lib().prolong_mrhs(op, _dptr(Q), int(q_dtype), int(n_tv), _dptr(yc), _dptr(y), int(y_dtype), int(n_rhs),
+                              _stream(stream)))
+
+
+def coarse_apply_mrhs(op, Dc, n_tv, yc, yc_out, n_rhs, stream=None):
+    _check(lib().coarse_apply_mrhs(op, _dptr(Dc), int(n_tv), _dptr(yc), _dptr(yc_out), int(n_rhs), _stream(stream)))
 
 
 def _arrays(ops, bs, xs, n_rhs):
@@ -216,6 +245,11 @@ class Operator:
         dt = self.dtype if dtype is None else dtype
         n = mrhs_vector_bytes(self.handle, n_rhs, dt) // torch.tensor([], dtype=TORCH_DTYPE[dt]).element_size()
         return torch.empty(n, dtype=TORCH_DTYPE[dt], device=self.device)
+
+    def coarse_empty(self, n_tv, n_rhs):
+        """FP32 coarse vectors (zeroed) for n_rhs right-hand sides of an n_tv-vector coarse grid."""
+        return torch.zeros(mrhs_coarse_vector_bytes(self.handle, n_tv, n_rhs) // 4, dtype=torch.float32,
+                           device=self.device)
 
     def workspace(self, n_rhs):
         return torch.empty(mrhs_workspace_bytes(self.handle, n_rhs), dtype=torch.uint8, device=self.device)

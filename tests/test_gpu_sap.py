@@ -123,3 +123,42 @@ def test_sap_c2_full_size_sampled():
         ref = oracle.sap(L, [4, 4, 4, 4], case.U, case.A, v[k:k + 1], 3, 4)
         assert per_rhs_rel(got[k:k + 1], ref) < 1e-5
     op.close()
+
+
+GUESS_CASES = [
+    # (L, block, sigma, seed, m0, prec, S, n, n_sap, n_mr, tile)
+    ([4, 4, 4, 4], [2, 2, 2, 2], 0.3, 101, -0.1, F64, 4, 8, 2, 3, 1),
+    ([8, 8, 4, 8], [4, 4, 4, 4], 0.3, 211, -0.3, F32, 4, 20, 3, 4, 2),
+    ([8, 8, 4, 8], [4, 4, 4, 4], 0.25, 311, -0.33, F16, 4, 6, 3, 4, 4),
+    ([6, 6, 2, 2], [2, 2, 2, 2], 0.3, 151, -0.2, F64, 2, 3, 2, 5, 2),     # odd counts: snapshot path
+    ([8, 4, 4, 4], [4, 4, 4, 4], 0.3, 171, -0.1, F32, 4, 5, 0, 3, 4),     # n_sap = 0 keeps the guess
+]
+
+
+@pytest.mark.parametrize("L,block,sigma,seed,m0,prec,S,n,n_sap,n_mr,tile", GUESS_CASES)
+def test_sap_from_guess_parity(L, block, sigma, seed, m0, prec, S, n, n_sap, n_mr, tile):
+    """SAP started from a given x (the refinement phase, Alg. 1 and 2) against the oracle."""
+    need_gpu()
+    case = Case(L, sigma, seed, m0)
+    announce("sap from guess L=%s prec=%d n=%d %dx%d" % (L, prec, n, n_sap, n_mr))
+    op = case.op(block, prec=prec, short_len=S)
+    mrhs.mrhs_set_tiles(op.handle, tile, 0)
+    v = inputs.test_vectors(L, n, seed + 1)
+    x0 = 0.3 * inputs.test_vectors(L, n, seed + 2)
+    b = op.pack(torch.from_numpy(v))
+    x = op.pack(torch.from_numpy(x0))
+    x0_read = op.unpack(x, n).cpu().numpy()  # the guess in the storage precision
+    mrhs.sap_smooth_mrhs_guess(op.handle, b, x, n, n_sap, n_mr, op.workspace(n))
+    got = op.unpack(x, n).cpu().numpy()
+    if n_sap == 0:
+        assert np.array_equal(got, x0_read)
+    else:
+        ref = oracle.sap(L, block, case.U, case.A, v, n_sap, n_mr, x0=x0_read)
+        assert per_rhs_rel(got, ref) < TOL[prec]
+    # from a zero guess the result is the initial-phase SAP, bit for bit
+    xz = op.empty(n)
+    xz.zero_()
+    mrhs.sap_smooth_mrhs_guess(op.handle, b, xz, n, n_sap, n_mr, op.workspace(n))
+    _, _, plain = run_sap(op, v, n_sap, n_mr)
+    assert np.array_equal(op.unpack(xz, n).cpu().numpy(), plain)
+    op.close()

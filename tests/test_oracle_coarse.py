@@ -197,3 +197,51 @@ def test_coarse_op_sampled_matches_full(setup_vectors):
     full = oracle.coarse_op(L4, A2, U, A, Q)
     part = oracle.coarse_op(L4, A2, U, A, Q, agg_list=[3, 12])
     assert np.array_equal(part[[3, 12]], full[[3, 12]])
+
+
+def _coarse_problem(L, a, n_tv, n, seed):
+    U = inputs.gauge_field(L, 0.3, seed)
+    A = oracle.clover(L, U, 1.0, -0.2)
+    Q = oracle.block_gs(L, a, inputs.test_vectors(L, n_tv, seed + 1))
+    Dc = oracle.coarse_op(L, a, U, A, Q)
+    Vc = oracle.n_aggregates(L, a)
+    rng = np.random.default_rng(seed + 2)
+    bc = rng.standard_normal((n, Vc, 2, n_tv)) + 1j * rng.standard_normal((n, Vc, 2, n_tv))
+    return Dc, bc
+
+
+def test_coarse_gmres_exact_and_minimal():
+    """GMRES on the coarse system (the low-accuracy coarse solve of Alg. 1): with as many
+    iterations as unknowns it solves exactly; one iteration is the minimal-residual step
+    u = alpha b, alpha = <D b, b> / <D b, D b>; the residual estimate is the true residual
+    and does not grow with the iteration count."""
+    L, a = [2, 2, 2, 4], [2, 2, 2, 2]
+    Dc, bc = _coarse_problem(L, a, 2, 2, 231)
+    Lc = [1, 1, 1, 2]
+    M = coarse_dense(Lc, Dc)
+    u, res, its = oracle.coarse_gmres(L, a, Dc, bc, m=8)
+    exact = np.linalg.solve(M, bc.reshape(2, -1).T).T.reshape(bc.shape)
+    assert rel(u, exact) < 1e-11 and np.all(res < 1e-11)
+    u1, _, its1 = oracle.coarse_gmres(L, a, Dc, bc, m=1)
+    for k in range(2):
+        bb = bc[k].reshape(-1)
+        db = M @ bb
+        alpha = np.vdot(db, bb) / np.vdot(db, db)
+        assert rel(u1[k].reshape(-1), alpha * bb) < 1e-13
+    assert np.all(its1 == 1)
+    L, a = L4, A2
+    Dc, bc = _coarse_problem(L, a, 4, 3, 241)
+    prev = np.full(3, np.inf)
+    for m in (1, 2, 4, 8):
+        u, res, its = oracle.coarse_gmres(L, a, Dc, bc, m=m)
+        true = np.linalg.norm((bc - oracle.coarse_apply(L, a, Dc, u)).reshape(3, -1), axis=1) / np.linalg.norm(
+            bc.reshape(3, -1), axis=1)
+        assert np.all(np.abs(true - res) < 1e-10 * true + 1e-14)
+        assert np.all(res <= prev * (1 + 1e-12))
+        prev = res
+    # a tolerance stops each right-hand side at the first iteration that reaches it
+    u, res, its = oracle.coarse_gmres(L, a, Dc, bc, m=30, tol=0.5)
+    assert np.all(res <= 0.5)
+    for k in range(3):
+        _, r_prev, _ = oracle.coarse_gmres(L, a, Dc, bc[k:k + 1], m=int(its[k]) - 1)
+        assert its[k] == 1 or r_prev[0] > 0.5

@@ -240,3 +240,29 @@ def test_block_spanning_direction_keeps_wrap_hop():
     bvec = inputs.test_vectors(L, 1, 162)
     x = oracle.sap(L, b, U, A, bvec, 1, 400)
     assert oracle.residual_norms(L, U, A, bvec, x)[0] < 1e-10
+
+
+def test_T9b_sap_from_guess():
+    """SAP from a starting guess (the refinement phase, Alg. 1 and 2): from zero it is the
+    initial-phase SAP, from the exact solution it stays there (zero residual, alpha = 0),
+    and sweeps compose (3 sweeps = 1 sweep, then 2 more from its result)."""
+    L, b = [2, 2, 2, 4], [2, 2, 2, 2]
+    U = inputs.gauge_field(L, 0.3, 181)
+    A = oracle.clover(L, U, 1.0, -0.1)
+    v = inputs.test_vectors(L, 2, 182)
+    assert np.array_equal(oracle.sap(L, b, U, A, v, 2, 3, x0=np.zeros_like(v)), oracle.sap(L, b, U, A, v, 2, 3))
+    V = 32
+    eye = np.eye(12 * V).reshape(12 * V, V, 4, 3)
+    D = oracle.dirac(L, U, A, eye).reshape(12 * V, 12 * V).T
+    xs = np.linalg.solve(D, v.reshape(2, -1).T).T.reshape(v.shape)
+    got = oracle.sap(L, b, U, A, v, 3, 4, x0=xs)
+    assert np.max(np.abs(got - xs)) < 1e-12 * np.max(np.abs(xs))
+    rng = np.random.default_rng(183)
+    x0 = rng.standard_normal(v.shape) + 1j * rng.standard_normal(v.shape)
+    three = oracle.sap(L, b, U, A, v, 3, 4, x0=x0)
+    one = oracle.sap(L, b, U, A, v, 1, 4, x0=x0)
+    assert np.array_equal(three, oracle.sap(L, b, U, A, v, 2, 4, x0=one))
+    # and it reduces the residual of a poor start
+    r0 = oracle.residual_norms(L, U, A, v, x0)
+    r3 = oracle.residual_norms(L, U, A, v, three)
+    assert np.all(r3 < 0.5 * r0)
