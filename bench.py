@@ -241,6 +241,52 @@ def coarse_grid_bench(mr, reps=20):
     return out
 
 
+def refinement_bench(mr, m=8, tol=0.05, reps=10):
+    """The refinement phase (Alg. 2 with N_b = N_tv): one pass = coarse-grid correction of
+    all test vectors (restrict, GMRES to tol, prolong), SAP from it, then the new R and D_c.
+    Also the paper's MRHS-vs-SRHS comparison for the coarse solve and the restriction: the
+    same calls on one right-hand side at a time, looped over the test vectors."""
+    op, n = mr.op, mr.n
+    D32 = mrhs.DTYPE_F32
+    ws = torch.empty(mrhs.mrhs_refine_workspace_bytes(op.handle, n, m), dtype=torch.uint8, device="cuda")
+    V = op.empty(n)
+    V.copy_(mr.x)
+
+    def refine():
+        mrhs.setup_refine_mrhs(op.handle, V, n, mr.Q, D32, mr.Dc, N_SAP, N_MR, m, tol, ws)
+
+    def rebuild():
+        mrhs.block_orthonormalize(op.handle, V, op.dtype, mr.Q, D32, n, mr.status, mr.ws)
+        mrhs.coarse_op_build(op.handle, mr.Q, D32, n, mr.Dc, mr.ws)
+
+    t_refine = time_call(refine, reps)
+    t_pass = time_call(lambda: (refine(), rebuild()), reps)
+    # coarse solve: all right-hand sides at once vs one at a time
+    bc, uc = op.coarse_empty(n, n), op.coarse_empty(n, n)
+    mrhs.restrict_mrhs(op.handle, mr.Q, D32, n, V, op.dtype, bc, n)
+    its = torch.zeros(n, dtype=torch.int32, device="cuda")
+    res = torch.zeros(n, dtype=torch.float64, device="cuda")
+    gws = torch.empty(mrhs.mrhs_coarse_solve_workspace_bytes(op.handle, n, n, m), dtype=torch.uint8, device="cuda")
+    t_cs = time_call(lambda: mrhs.coarse_solve_mrhs(op.handle, mr.Dc, n, bc, uc, n, m, tol, gws, res, its), reps)
+    b1, u1 = op.coarse_empty(n, 1), op.coarse_empty(n, 1)
+    gws1 = torch.empty(mrhs.mrhs_coarse_solve_workspace_bytes(op.handle, n, 1, m), dtype=torch.uint8, device="cuda")
+    t_cs1 = time_call(lambda: [mrhs.coarse_solve_mrhs(op.handle, mr.Dc, n, b1, u1, 1, m, tol, gws1) for _ in range(n)],
+                      max(2, reps // 4))
+    t_r = time_call(lambda: mrhs.restrict_mrhs(op.handle, mr.Q, D32, n, V, op.dtype, bc, n), reps)
+    y1 = op.empty(1)
+    t_r1 = time_call(lambda: [mrhs.restrict_mrhs(op.handle, mr.Q, D32, n, y1, op.dtype, b1, 1) for _ in range(n)],
+                     max(2, reps // 4))
+    torch.cuda.synchronize()
+    return {"gmres_max_iter": m, "tol": tol, "iterations_needed": int(its.max().item()),
+            "coarse_residual_max": float(res.max().item()),
+            "refine_ms": round(t_refine, 4), "refine_pass_with_rebuild_ms": round(t_pass, 4),
+            "refine_site_rhs_per_s": int(np.prod(L)) * n * N_SAP / (t_pass * 1e-3),
+            "coarse_solve_mrhs_ms": round(t_cs, 4), "coarse_solve_srhs_looped_ms": round(t_cs1, 4),
+            "coarse_solve_speedup": round(t_cs1 / t_cs, 2),
+            "restrict_mrhs_ms": round(t_r, 4), "restrict_srhs_looped_ms": round(t_r1, 4),
+            "restrict_speedup": round(t_r1 / t_r, 2)}
+
+
 def cpu_baseline(U, v, x_gpu, budget_s=30.0):
     """The oracle on the host cores: SAP on a sample of test vectors (they are independent),
     Gram-Schmidt on all aggregates, D_c on a sample of aggregates; scaled to the full step."""
@@ -360,6 +406,10 @@ def main():
     coarse_grid = coarse_grid_bench(mr)
     log("coarse grid %s" % coarse_grid)
 
+    log("refinement phase")
+    refinement = refinement_bench(mr)
+    log("refinement %s" % refinement)
+
     batched = None
     if not args.no_batched:
         log("batched uneven lattices")
@@ -396,6 +446,7 @@ def main():
         "sap": sap_info,
         "srhs": srhs,
         "coarse_grid": coarse_grid,
+        "refinement": refinement,
         "batched": batched,
         "cpu_baseline": cpu,
     }

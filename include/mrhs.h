@@ -178,6 +178,33 @@ int prolong_mrhs(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv
 int coarse_apply_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const float *yc, float *yc_out,
                       int32_t n_rhs, void *stream);
 
+/* uc ~ D_c^-1 bc, the low-accuracy coarse solve of the refinement phase (Alg. 1), for all
+ * right-hand sides at once: GMRES from a zero start, at most m (1..64) iterations, Arnoldi
+ * with classical Gram-Schmidt applied twice, complex Givens rotations; a right-hand side
+ * stops once its residual estimate falls to tol * ||bc_k|| (tol = 0: m iterations, fewer
+ * only at an exact solution).  Vectors FP32, inner products and the small Hessenberg
+ * algebra FP64.  res_out (DEVICE double[n_rhs], nullable): final estimate / ||bc_k||;
+ * iters_out (DEVICE int32[n_rhs], nullable): iterations taken.  ws: at least
+ * mrhs_coarse_solve_workspace_bytes(op, n_tv, n_rhs, m) bytes (Krylov bases of all
+ * right-hand sides).  uc must not overlap bc, Dc or ws.  The call enqueues a fixed sequence
+ * of launches (no host synchronisation). */
+size_t mrhs_coarse_solve_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m);
+int coarse_solve_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const float *bc, float *uc, int32_t n_rhs,
+                      int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* One pass of the refinement phase over all test vectors at once (Alg. 2 with the block
+ * length N_b = n_tv, Alg. 1's loop body for every vector): v_c = R v, u_c ~ D_c^-1 v_c
+ * (coarse_solve_mrhs: m iterations, tolerance tol), u = P u_c, then x = SAP(v) started
+ * from u (sap_smooth_mrhs_guess: n_sap x n_mr), and v is replaced by x.  V: n_tv native
+ * test vectors of the op's element type, overwritten; Q, Dc: the current R = Q^dag and
+ * D_c (from block_orthonormalize and coarse_op_build on the previous V), not overlapping V.
+ * Rebuilding Q and D_c from the new V is the caller's next step (Alg. 2, last line).
+ * ws: at least mrhs_refine_workspace_bytes(op, n_tv, m) bytes. */
+size_t mrhs_refine_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t m);
+int setup_refine_mrhs(const mrhs_op *op, void *V, int32_t n_tv, const void *Q, int32_t q_dtype, const float *Dc,
+                      int32_t n_sap, int32_t n_mr, int32_t m, double tol, void *ws, size_t ws_bytes, void *stream);
+
 /* SAP on several operators at once -- lattices of uneven size, each with its own
  * right-hand sides -- with one launch per half-sweep for the whole batch (the loop over
  * test vectors and over lattices moved into the kernel, Sec. 3).  The enqueued work is a

@@ -4,7 +4,7 @@
 #include <cstring>
 #include <vector>
 
-#include "internal.h"
+#include "launch.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -438,6 +438,53 @@ int coarse_apply_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const fl
         ranges_overlap(yc_out, cb, Dc, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(float)))
         return set_error(MRHS_EINVAL, "coarse output overlaps an input");
     return launch_coarse_apply(op, Dc, n_tv, yc, yc_out, n_rhs, (hipStream_t)stream);
+}
+
+size_t mrhs_coarse_solve_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m)
+{
+    if (!op || n_tv <= 0 || n_rhs <= 0 || m <= 0) return 0;
+    return ws_bytes_coarse_solve(op, n_tv, n_rhs, m);
+}
+
+int coarse_solve_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const float *bc, float *uc, int32_t n_rhs,
+                      int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, MRHS_DTYPE_F32)) return rc;
+    if (!Dc || !bc || !uc) return set_error(MRHS_EINVAL, "null argument");
+    if (m < 1 || m > 64) return set_error(MRHS_EINVAL, "iteration count must be 1..64");
+    if (!(tol >= 0.0)) return set_error(MRHS_EINVAL, "tolerance must be >= 0");
+    const size_t need = ws_bytes_coarse_solve(op, n_tv, n_rhs, m);
+    if (!ws || ws_bytes < need) return set_error(MRHS_EINVAL, "workspace too small");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    if (ranges_overlap(uc, cb, bc, cb) || ranges_overlap(uc, cb, ws, need) || ranges_overlap(bc, cb, ws, need) ||
+        ranges_overlap(uc, cb, Dc, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(float)))
+        return set_error(MRHS_EINVAL, "coarse vectors overlap each other, D_c or the workspace");
+    return launch_coarse_solve(op, Dc, n_tv, bc, uc, n_rhs, m, tol, res_out, iters_out, ws, (hipStream_t)stream);
+}
+
+size_t mrhs_refine_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t m)
+{
+    if (!op || n_tv <= 0 || m <= 0) return 0;
+    return ws_bytes_refine(op, n_tv, m);
+}
+
+int setup_refine_mrhs(const mrhs_op *op, void *V, int32_t n_tv, const void *Q, int32_t q_dtype, const float *Dc,
+                      int32_t n_sap, int32_t n_mr, int32_t m, double tol, void *ws, size_t ws_bytes, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_tv, q_dtype)) return rc;
+    if (!V || !Q || !Dc) return set_error(MRHS_EINVAL, "null argument");
+    if (n_sap < 0 || n_mr < 0) return set_error(MRHS_EINVAL, "negative iteration count");
+    if (m < 1 || m > 64) return set_error(MRHS_EINVAL, "iteration count must be 1..64");
+    if (!(tol >= 0.0)) return set_error(MRHS_EINVAL, "tolerance must be >= 0");
+    const size_t need = ws_bytes_refine(op, n_tv, m);
+    if (!ws || ws_bytes < need) return set_error(MRHS_EINVAL, "workspace too small");
+    const size_t vb = native_elems(op, n_tv) * dtype_size(op->dtype);
+    const size_t qb = native_elems(op, n_tv) * dtype_size(q_dtype);
+    if (ranges_overlap(V, vb, Q, qb) || ranges_overlap(ws, need, V, vb) || ranges_overlap(ws, need, Q, qb) ||
+        ranges_overlap(ws, need, Dc, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(float)))
+        return set_error(MRHS_EINVAL, "test vectors, Q, D_c and the workspace must not overlap");
+    return launch_refine(op, V, n_tv, Q, q_dtype, Dc, n_sap, n_mr, m, tol, ws, (hipStream_t)stream);
 }
 
 size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const int32_t *n_rhs)

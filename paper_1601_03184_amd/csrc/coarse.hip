@@ -19,6 +19,7 @@
 //                 sigma3 relation
 #include <algorithm>
 
+#include "launch.h"
 #include "stencil.h"
 
 namespace {

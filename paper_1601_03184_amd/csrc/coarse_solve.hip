@@ -1,0 +1,344 @@
+// coarse_solve.hip -- the low-accuracy coarse solve of the refinement phase (Alg. 1, 2:
+// u_c ~ D_c^-1 v_c) on all right-hand sides at once: GMRES from a zero start, Arnoldi
+// with classical Gram-Schmidt applied twice, complex Givens rotations.  Every right-hand
+// side has its own Krylov basis; one launch of each step serves all of them, and the
+// operator is applied to all of them in one coarse_apply (the mat-mat form of Sec. 6).
+//
+// Vectors are FP32 (coarse layout of transfer.hip); inner products, norms, the Hessenberg
+// matrix, the rotations and the small triangular solve are FP64.  A right-hand side whose
+// residual estimate has reached tol * ||b|| stops taking part (its later basis vectors are
+// zero and its Hessenberg matrix is frozen), so the host issues a fixed sequence of
+// launches without reading anything back.
+#include <algorithm>
+
+#include "launch.h"
+
+namespace {
+
+struct Z {
+    double re, im;
+};
+__device__ inline Z zmul(Z a, Z b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Z zconjmul(Z a, Z b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
+
+constexpr int GTHR = 256;
+constexpr int GROWS = GTHR / 32;  // element rows per block pass (32 right-hand-side lanes)
+
+struct GmArgs {
+    int n, ldc, m;
+    long dim;     // complex entries per right-hand side (coarse sites x 2 n_tv)
+    long cvlen;   // floats of one coarse vector
+    int G;        // reduction blocks
+    double tol;
+    float *V;     // (m + 1) coarse vectors
+    float *w;
+    Z *part;      // [G][m + 1][ldc]
+    Z *hcur;      // [ldc][m + 1]: the current inner products, then y
+    Z *H;         // [ldc][m + 1][m]
+    Z *g;         // [ldc][m + 1]
+    Z *sn;        // [ldc][m]
+    double *cs;   // [ldc][m]
+    double *beta, *est, *scale;  // [ldc]
+    int *J, *active;             // [ldc]
+};
+
+// element (e, k) of a coarse vector: entry e = site * 2 n_tv + dof, right-hand side k
+__device__ inline long cre(const GmArgs &a, long e, int k) { return (2 * e) * a.ldc + k; }
+
+// part[blk][i][k] = sum over this block's entries of conj(X_i) y, X_i = X + i * xstride
+__global__ void __launch_bounds__(GTHR) k_gm_dots(GmArgs a, const float *X, long xstride, int nvec, const float *y)
+{
+    __shared__ Z red[GROWS][32];
+    const int i = blockIdx.y;
+    const int k = threadIdx.x & 31, row = threadIdx.x >> 5;
+    const long chunk = (a.dim + a.G - 1) / a.G, e0 = blockIdx.x * chunk, e1 = e0 + chunk < a.dim ? e0 + chunk : a.dim;
+    const float *xi = X + i * xstride;
+    Z s = {0.0, 0.0};
+    if (k < a.ldc)
+        for (long e = e0 + row; e < e1; e += GROWS) {
+            const long o = cre(a, e, k);
+            const Z xv = {xi[o], xi[o + a.ldc]}, yv = {y[o], y[o + a.ldc]};
+            const Z p = zconjmul(xv, yv);
+            s.re += p.re;
+            s.im += p.im;
+        }
+    red[row][k] = s;
+    __syncthreads();
+    if (row == 0 && k < a.ldc) {
+        Z t = red[0][k];
+        for (int r = 1; r < GROWS; ++r) {
+            t.re += red[r][k].re;
+            t.im += red[r][k].im;
+        }
+        a.part[((long)blockIdx.x * (a.m + 1) + i) * a.ldc + k] = t;
+    }
+    (void)nvec;
+}
+
+// hcur[k][i] = sum over blocks in order; mode 1: also H[k][i][col] += hcur (active only)
+__global__ void k_gm_dots_finish(GmArgs a, int nvec, int col, int mode)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nvec * a.ldc) return;
+    const int i = t / a.ldc, k = t - i * a.ldc;
+    Z s = {0.0, 0.0};
+    for (int b = 0; b < a.G; ++b) {
+        const Z p = a.part[((long)b * (a.m + 1) + i) * a.ldc + k];
+        s.re += p.re;
+        s.im += p.im;
+    }
+    a.hcur[(long)k * (a.m + 1) + i] = s;
+    if (mode == 1 && a.active[k]) {
+        Z &h = a.H[((long)k * (a.m + 1) + i) * a.m + col];
+        h.re += s.re;
+        h.im += s.im;
+    }
+}
+
+// w -= sum_i hcur[k][i] V_i   (i < nvec)
+__global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.dim * a.ldc) return;
+    const long e = t / a.ldc;
+    const int k = (int)(t - e * a.ldc);
+    const long o = cre(a, e, k);
+    double wr = a.w[o], wi = a.w[o + a.ldc];
+    for (int i = 0; i < nvec; ++i) {
+        const Z h = a.hcur[(long)k * (a.m + 1) + i];
+        const float *vi = a.V + i * a.cvlen;
+        const Z v = {vi[o], vi[o + a.ldc]};
+        const Z p = zmul(h, v);
+        wr -= p.re;
+        wi -= p.im;
+    }
+    a.w[o] = (float)wr;
+    a.w[o + a.ldc] = (float)wi;
+}
+
+// start: beta = ||b|| (hcur[k][0] holds ||b||^2), g = (beta, 0, ...), H = 0, V_0 = b / beta
+__global__ void k_gm_start(GmArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.ldc) return;
+    const double b = sqrt(a.hcur[(long)k * (a.m + 1)].re);
+    a.beta[k] = b;
+    a.est[k] = b;
+    a.J[k] = 0;
+    a.active[k] = k < a.n && b > 0.0 && b > a.tol * b;
+    a.scale[k] = b > 0.0 ? 1.0 / b : 0.0;
+    for (int i = 0; i <= a.m; ++i) a.g[(long)k * (a.m + 1) + i] = {i == 0 ? b : 0.0, 0.0};
+    for (long e = 0; e < (long)(a.m + 1) * a.m; ++e) a.H[(long)k * (a.m + 1) * a.m + e] = {0.0, 0.0};
+}
+
+// V_dst = src * scale[k]
+__global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, float *dst)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.dim * a.ldc) return;
+    const long e = t / a.ldc;
+    const int k = (int)(t - e * a.ldc);
+    const long o = cre(a, e, k);
+    const double s = a.scale[k];
+    dst[o] = (float)(src[o] * s);
+    dst[o + a.ldc] = (float)(src[o + a.ldc] * s);
+}
+
+// iteration j: ||w|| -> H[j+1][j], the earlier rotations on column j, a new rotation, g,
+// the residual estimate and whether the right-hand side continues; scale = 1 / ||w||
+__global__ void k_gm_givens(GmArgs a, int j)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.ldc) return;
+    if (!a.active[k]) {
+        a.scale[k] = 0.0;
+        return;
+    }
+    const int m = a.m;
+    Z *H = a.H + (long)k * (m + 1) * m;
+    Z *g = a.g + (long)k * (m + 1);
+    double *cs = a.cs + (long)k * m;
+    Z *sn = a.sn + (long)k * m;
+    const double nw = sqrt(a.hcur[(long)k * (m + 1)].re);
+    for (int i = 0; i < j; ++i) {
+        const Z x0 = H[i * m + j], x1 = H[(i + 1) * m + j];
+        const Z s1 = zmul(sn[i], x1), s0 = zmul({sn[i].re, -sn[i].im}, x0);
+        H[i * m + j] = {cs[i] * x0.re + s1.re, cs[i] * x0.im + s1.im};
+        H[(i + 1) * m + j] = {-s0.re + cs[i] * x1.re, -s0.im + cs[i] * x1.im};
+    }
+    const Z hj = H[j * m + j];
+    const double ah = sqrt(hj.re * hj.re + hj.im * hj.im), rho = sqrt(ah * ah + nw * nw);
+    if (ah == 0.0) {
+        cs[j] = 0.0;
+        sn[j] = {1.0, 0.0};
+    } else {
+        cs[j] = ah / rho;
+        sn[j] = {hj.re / ah * nw / rho, hj.im / ah * nw / rho};
+    }
+    H[j * m + j] = {cs[j] * hj.re + sn[j].re * nw, cs[j] * hj.im + sn[j].im * nw};
+    H[(j + 1) * m + j] = {0.0, 0.0};
+    const Z gj = g[j];
+    const Z t = zmul({sn[j].re, -sn[j].im}, gj);
+    g[j + 1] = {-t.re, -t.im};
+    g[j] = {cs[j] * gj.re, cs[j] * gj.im};
+    const double est = sqrt(g[j + 1].re * g[j + 1].re + g[j + 1].im * g[j + 1].im);
+    a.est[k] = est;
+    a.J[k] = j + 1;
+    a.active[k] = nw > 0.0 && est > a.tol * a.beta[k];
+    a.scale[k] = nw > 0.0 ? 1.0 / nw : 0.0;
+}
+
+// y = H^-1 g (back substitution over the J[k] iterations taken), into hcur
+__global__ void k_gm_solve(GmArgs a, double *res_out, int32_t *iters_out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.ldc) return;
+    const int m = a.m, J = a.J[k];
+    const Z *H = a.H + (long)k * (m + 1) * m;
+    const Z *g = a.g + (long)k * (m + 1);
+    Z *y = a.hcur + (long)k * (m + 1);
+    for (int i = 0; i <= m; ++i) y[i] = {0.0, 0.0};
+    for (int i = J - 1; i >= 0; --i) {
+        Z s = g[i];
+        for (int l = i + 1; l < J; ++l) {
+            const Z p = zmul(H[i * m + l], y[l]);
+            s.re -= p.re;
+            s.im -= p.im;
+        }
+        const Z d = H[i * m + i];
+        const double dd = d.re * d.re + d.im * d.im;
+        y[i] = {(s.re * d.re + s.im * d.im) / dd, (s.im * d.re - s.re * d.im) / dd};
+    }
+    if (k < a.n) {
+        if (res_out) res_out[k] = a.beta[k] > 0.0 ? a.est[k] / a.beta[k] : 0.0;
+        if (iters_out) iters_out[k] = J;
+    }
+}
+
+// u = sum_i y_i V_i
+__global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.dim * a.ldc) return;
+    const long e = t / a.ldc;
+    const int k = (int)(t - e * a.ldc);
+    const long o = cre(a, e, k);
+    double ur = 0.0, ui = 0.0;
+    const int J = a.J[k];
+    for (int i = 0; i < J; ++i) {
+        const Z y = a.hcur[(long)k * (a.m + 1) + i];
+        const float *vi = a.V + i * a.cvlen;
+        const Z v = {vi[o], vi[o + a.ldc]};
+        const Z p = zmul(y, v);
+        ur += p.re;
+        ui += p.im;
+    }
+    u[o] = k < a.n ? (float)ur : 0.f;
+    u[o + a.ldc] = k < a.n ? (float)ui : 0.f;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// workspace layout for (op, n_tv, n, m); fills the pointers when base != nullptr
+size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *a)
+{
+    const int ldc = (n + 3) / 4 * 4;
+    const long dim = (long)op->n_agg * 2 * n_tv;
+    const long cvlen = dim * 2 * ldc;
+    const int G = (int)std::min<long>(512, std::max<long>(1, (dim + 255) / 256));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    char *V = take(sizeof(float) * cvlen * (m + 1));
+    char *w = take(sizeof(float) * cvlen);
+    char *part = take(sizeof(Z) * (size_t)G * (m + 1) * ldc);
+    char *hcur = take(sizeof(Z) * (size_t)ldc * (m + 1));
+    char *H = take(sizeof(Z) * (size_t)ldc * (m + 1) * m);
+    char *g = take(sizeof(Z) * (size_t)ldc * (m + 1));
+    char *sn = take(sizeof(Z) * (size_t)ldc * m);
+    char *cs = take(sizeof(double) * (size_t)ldc * m);
+    char *beta = take(sizeof(double) * ldc);
+    char *est = take(sizeof(double) * ldc);
+    char *scale = take(sizeof(double) * ldc);
+    char *J = take(sizeof(int) * ldc);
+    char *act = take(sizeof(int) * ldc);
+    if (a) {
+        a->n = n;
+        a->ldc = ldc;
+        a->m = m;
+        a->dim = dim;
+        a->cvlen = cvlen;
+        a->G = G;
+        a->V = (float *)V;
+        a->w = (float *)w;
+        a->part = (Z *)part;
+        a->hcur = (Z *)hcur;
+        a->H = (Z *)H;
+        a->g = (Z *)g;
+        a->sn = (Z *)sn;
+        a->cs = (double *)cs;
+        a->beta = (double *)beta;
+        a->est = (double *)est;
+        a->scale = (double *)scale;
+        a->J = (int *)J;
+        a->active = (int *)act;
+    }
+    return off;
+}
+
+}  // namespace
+
+size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m) { return gm_layout(op, n_tv, n, m, nullptr, nullptr); }
+
+int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
+                        double *res_out, int32_t *iters_out, void *ws, hipStream_t st)
+{
+    GmArgs a{};
+    gm_layout(op, n_tv, n, m, (char *)ws, &a);
+    a.tol = tol;
+    const long nel = a.dim * a.ldc;
+    const int eb = (int)((nel + GTHR - 1) / GTHR);
+    const int kb = (a.ldc + 63) / 64;
+#define GM_CHECK(what) \
+    if (int rc = hip_check(hipGetLastError(), what)) return rc
+    // beta, V_0
+    hipLaunchKernelGGL(k_gm_dots, dim3(a.G, 1), dim3(GTHR), 0, st, a, b, 0L, 1, b);
+    GM_CHECK("k_gm_dots launch");
+    hipLaunchKernelGGL(k_gm_dots_finish, dim3((a.ldc + 63) / 64), dim3(64), 0, st, a, 1, 0, 0);
+    GM_CHECK("k_gm_dots_finish launch");
+    hipLaunchKernelGGL(k_gm_start, dim3(kb), dim3(64), 0, st, a);
+    GM_CHECK("k_gm_start launch");
+    hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, b, a.V);
+    GM_CHECK("k_gm_scale launch");
+    for (int j = 0; j < m; ++j) {
+        float *vj = a.V + (long)j * a.cvlen;
+        if (int rc = launch_coarse_apply(op, Dc, n_tv, vj, a.w, n, st)) return rc;
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_gm_dots, dim3(a.G, j + 1), dim3(GTHR), 0, st, a, (const float *)a.V, a.cvlen, j + 1,
+                               (const float *)a.w);
+            GM_CHECK("k_gm_dots launch");
+            hipLaunchKernelGGL(k_gm_dots_finish, dim3(((j + 1) * a.ldc + 63) / 64), dim3(64), 0, st, a, j + 1, j, 1);
+            GM_CHECK("k_gm_dots_finish launch");
+            hipLaunchKernelGGL(k_gm_axpy, dim3(eb), dim3(GTHR), 0, st, a, j + 1);
+            GM_CHECK("k_gm_axpy launch");
+        }
+        hipLaunchKernelGGL(k_gm_dots, dim3(a.G, 1), dim3(GTHR), 0, st, a, (const float *)a.w, 0L, 1,
+                           (const float *)a.w);
+        GM_CHECK("k_gm_dots launch");
+        hipLaunchKernelGGL(k_gm_dots_finish, dim3((a.ldc + 63) / 64), dim3(64), 0, st, a, 1, 0, 0);
+        GM_CHECK("k_gm_dots_finish launch");
+        hipLaunchKernelGGL(k_gm_givens, dim3(kb), dim3(64), 0, st, a, j);
+        GM_CHECK("k_gm_givens launch");
+        hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, (const float *)a.w, a.V + (long)(j + 1) * a.cvlen);
+        GM_CHECK("k_gm_scale launch");
+    }
+    hipLaunchKernelGGL(k_gm_solve, dim3(kb), dim3(64), 0, st, a, res_out, iters_out);
+    GM_CHECK("k_gm_solve launch");
+    hipLaunchKernelGGL(k_gm_combine, dim3(eb), dim3(GTHR), 0, st, a, u);
+    GM_CHECK("k_gm_combine launch");
+#undef GM_CHECK
+    return MRHS_OK;
+}

@@ -5,6 +5,7 @@
 // and one right-hand side.  The T lanes of a site issue the same link and clover loads,
 // so the operator is fetched once per site for the whole tile (the mat-vec -> mat-mat
 // argument of Sec. 6); tiles of one block share an XCD's L2 through xcd_remap.
+#include "launch.h"
 #include "stencil.h"
 
 namespace {

@@ -2,7 +2,7 @@
 // site order (the 4 forward links of a site side by side, scaled by -1/2) and build the
 // site term A(x) = (4 + m0) + C(x) as two Hermitian 6x6 blocks (chiral halves), in FP64;
 // FP32 copies for the FP32 operators.
-#include "internal.h"
+#include "launch.h"
 
 namespace {
 

@@ -22,7 +22,7 @@
 #include <algorithm>
 #include <climits>
 
-#include "internal.h"
+#include "launch.h"
 
 namespace {
 

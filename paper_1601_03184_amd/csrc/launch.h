@@ -1,0 +1,38 @@
+// launch.h -- host-side launchers and workspace sizes of the library's kernels (one per
+// source file), used by the C-ABI in abi.hip.
+#pragma once
+
+#include "internal.h"
+
+int launch_build_fields(mrhs_op *op, const double *links_canon, double m0, double csw, hipStream_t st);
+int launch_pack(const mrhs_op *op, const double *canon, void *native, int dtype, int n_rhs, int *flag, hipStream_t st);
+int launch_unpack(const mrhs_op *op, const void *native, int dtype, double *canon, int n_rhs, hipStream_t st);
+int launch_dirac(const mrhs_op *op, const void *x, void *y, int n_rhs, hipStream_t st);
+int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st,
+               bool guess = false);
+int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st);
+int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *ws,
+              hipStream_t st);
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st);
+size_t ws_bytes_sap(const mrhs_op *op, int n_rhs);
+size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs);
+int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
+                       int n_sap, int n_mr, void *ws, hipStream_t st, bool guess = false);
+size_t ws_bytes_residual(const mrhs_op *op, int n_rhs);
+size_t ws_bytes_gs(const mrhs_op *op, int n_tv);
+size_t ws_bytes_coarse(const mrhs_op *op, int n_tv);
+size_t native_elems(const mrhs_op *op, int n_rhs);
+int dtype_size(int dtype);
+int launch_restrict(const mrhs_op *op, const void *Q, int qdt, int n_tv, const void *y, int ydt, float *yc, int n,
+                    hipStream_t st);
+int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const float *yc, void *y, int ydt, int n,
+                   hipStream_t st);
+int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,
+                        hipStream_t st);
+size_t transfer_lds_bytes(const mrhs_op *op);
+size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m);
+int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
+                        double *res_out, int32_t *iters_out, void *ws, hipStream_t st);
+size_t ws_bytes_refine(const mrhs_op *op, int n_tv, int m);
+int launch_refine(const mrhs_op *op, void *V, int n_tv, const void *Q, int qdt, const float *Dc, int n_sap, int n_mr,
+                  int m, double tol, void *ws, hipStream_t st);

@@ -14,6 +14,7 @@
 // The links and clover of a site are loaded once per stencil for all T lanes of the site.
 #include <algorithm>
 
+#include "launch.h"
 #include "stencil.h"
 
 namespace {

@@ -15,7 +15,7 @@
 // at ((i * 2 n_tv + c) * 2 + p) * ldc + k, ldc = n rounded up to a multiple of 4.
 #include <algorithm>
 
-#include "internal.h"
+#include "launch.h"
 
 namespace {
 

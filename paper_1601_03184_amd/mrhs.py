@@ -62,6 +62,10 @@ def lib():
             "restrict_mrhs": (i32, [p, p, i32, i32, p, i32, p, i32, p]),
             "prolong_mrhs": (i32, [p, p, i32, i32, p, p, i32, i32, p]),
             "coarse_apply_mrhs": (i32, [p, p, i32, p, p, i32, p]),
+            "mrhs_coarse_solve_workspace_bytes": (sz, [p, i32, i32, i32]),
+            "coarse_solve_mrhs": (i32, [p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
+            "mrhs_refine_workspace_bytes": (sz, [p, i32, i32]),
+            "setup_refine_mrhs": (i32, [p, p, i32, p, i32, p, i32, i32, i32, d, p, sz, p]),
             "mrhs_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -182,6 +186,26 @@ def prolong_mrhs(op, Q, q_dtype, n_tv, yc, y, y_dtype, n_rhs, stream=None):
 
 def coarse_apply_mrhs(op, Dc, n_tv, yc, yc_out, n_rhs, stream=None):
     _check(lib().coarse_apply_mrhs(op, _dptr(Dc), int(n_tv), _dptr(yc), _dptr(yc_out), int(n_rhs), _stream(stream)))
+
+
+def mrhs_coarse_solve_workspace_bytes(op, n_tv, n_rhs, m):
+    return lib().mrhs_coarse_solve_workspace_bytes(op, int(n_tv), int(n_rhs), int(m))
+
+
+def coarse_solve_mrhs(op, Dc, n_tv, bc, uc, n_rhs, m, tol, ws, res_out=None, iters_out=None, stream=None):
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().coarse_solve_mrhs(op, _dptr(Dc), int(n_tv), _dptr(bc), _dptr(uc), int(n_rhs), int(m), float(tol),
+                                   _dptr(res_out), _dptr(iters_out), _dptr(ws), nb, _stream(stream)))
+
+
+def mrhs_refine_workspace_bytes(op, n_tv, m):
+    return lib().mrhs_refine_workspace_bytes(op, int(n_tv), int(m))
+
+
+def setup_refine_mrhs(op, V, n_tv, Q, q_dtype, Dc, n_sap, n_mr, m, tol, ws, stream=None):
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().setup_refine_mrhs(op, _dptr(V), int(n_tv), _dptr(Q), int(q_dtype), _dptr(Dc), int(n_sap), int(n_mr),
+                                   int(m), float(tol), _dptr(ws), nb, _stream(stream)))
 
 
 def _arrays(ops, bs, xs, n_rhs):
