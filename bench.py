@@ -47,8 +47,8 @@ FP32_ISSUE_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4
 # with (SHA-1 of the files below); otherwise the bench reports traffic as null.
 SAP_SOURCES = ["paper_1601_03184_amd/csrc/sap.hip", "paper_1601_03184_amd/csrc/stencil.h",
                "paper_1601_03184_amd/csrc/internal.h"]
-SAP_TRAFFIC = {"sources_sha1": "c75333a1fdcf6faeb7f3b4dd04b4a895461e91bd", "fetch_scale": 2.0, "write_scale": 1.0,
-               "kib": {1: (193676, 86301), 2: (189023, 64740), 4: (208262, 71680)}}
+SAP_TRAFFIC = {"sources_sha1": "01bb876324c7795287cd5a7f2c0e4364442f0d8d", "fetch_scale": 2.0, "write_scale": 1.0,
+               "kib": {1: (191433, 85677), 2: (187658, 65027), 4: (205965, 71680)}}
 
 
 def sap_traffic_bytes(tile):
@@ -333,6 +333,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-srhs", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-refine", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -406,9 +407,11 @@ def main():
     coarse_grid = coarse_grid_bench(mr)
     log("coarse grid %s" % coarse_grid)
 
-    log("refinement phase")
-    refinement = refinement_bench(mr)
-    log("refinement %s" % refinement)
+    refinement = None
+    if not args.no_refine:
+        log("refinement phase")
+        refinement = refinement_bench(mr)
+        log("refinement %s" % refinement)
 
     batched = None
     if not args.no_batched:
