@@ -22,17 +22,17 @@ __device__ inline Z zmul(Z a, Z b) { return {a.re * b.re - a.im * b.im, a.re * b
 __device__ inline Z zconjmul(Z a, Z b) { return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re}; }  // conj(a) b
 
 constexpr int GTHR = 256;
-constexpr int GROWS = GTHR / 32;  // element rows per block pass (32 right-hand-side lanes)
+constexpr int DTHR = 512;
+constexpr int DROWS = DTHR / 32;  // element rows per block pass of the inner products (32 right-hand-side lanes)
 
 struct GmArgs {
     int n, ldc, m;
     long dim;     // complex entries per right-hand side (coarse sites x 2 n_tv)
     long cvlen;   // floats of one coarse vector
-    int G;        // reduction blocks
     double tol;
     float *V;     // (m + 1) coarse vectors
     float *w;
-    Z *part;      // [G][m + 1][ldc]
+    Z *part;      // [vectors][G][ldc] partial inner products, G x vectors <= GPART
     Z *hcur;      // [ldc][m + 1]: the current inner products, then y
     Z *H;         // [ldc][m + 1][m]
     Z *g;         // [ldc][m + 1]
@@ -45,83 +45,12 @@ struct GmArgs {
 // element (e, k) of a coarse vector: entry e = site * 2 n_tv + dof, right-hand side k
 __device__ inline long cre(const GmArgs &a, long e, int k) { return (2 * e) * a.ldc + k; }
 
-// part[blk][i][k] = sum over this block's entries of conj(X_i) y, X_i = X + i * xstride
-__global__ void __launch_bounds__(GTHR) k_gm_dots(GmArgs a, const float *X, long xstride, int nvec, const float *y)
-{
-    __shared__ Z red[GROWS][32];
-    const int i = blockIdx.y;
-    const int k = threadIdx.x & 31, row = threadIdx.x >> 5;
-    const long chunk = (a.dim + a.G - 1) / a.G, e0 = blockIdx.x * chunk, e1 = e0 + chunk < a.dim ? e0 + chunk : a.dim;
-    const float *xi = X + i * xstride;
-    Z s = {0.0, 0.0};
-    if (k < a.ldc)
-        for (long e = e0 + row; e < e1; e += GROWS) {
-            const long o = cre(a, e, k);
-            const Z xv = {xi[o], xi[o + a.ldc]}, yv = {y[o], y[o + a.ldc]};
-            const Z p = zconjmul(xv, yv);
-            s.re += p.re;
-            s.im += p.im;
-        }
-    red[row][k] = s;
-    __syncthreads();
-    if (row == 0 && k < a.ldc) {
-        Z t = red[0][k];
-        for (int r = 1; r < GROWS; ++r) {
-            t.re += red[r][k].re;
-            t.im += red[r][k].im;
-        }
-        a.part[((long)blockIdx.x * (a.m + 1) + i) * a.ldc + k] = t;
-    }
-    (void)nvec;
-}
+constexpr int GPART = 512;  // partial-sum blocks per inner-product launch (all vectors together)
 
-// hcur[k][i] = sum over blocks in order; mode 1: also H[k][i][col] += hcur (active only)
-__global__ void k_gm_dots_finish(GmArgs a, int nvec, int col, int mode)
+// start: beta = ||b|| (from ||b||^2), g = (beta, 0, ...), H = 0, scale = 1 / beta
+__device__ void gm_start(const GmArgs &a, int k, double b2)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nvec * a.ldc) return;
-    const int i = t / a.ldc, k = t - i * a.ldc;
-    Z s = {0.0, 0.0};
-    for (int b = 0; b < a.G; ++b) {
-        const Z p = a.part[((long)b * (a.m + 1) + i) * a.ldc + k];
-        s.re += p.re;
-        s.im += p.im;
-    }
-    a.hcur[(long)k * (a.m + 1) + i] = s;
-    if (mode == 1 && a.active[k]) {
-        Z &h = a.H[((long)k * (a.m + 1) + i) * a.m + col];
-        h.re += s.re;
-        h.im += s.im;
-    }
-}
-
-// w -= sum_i hcur[k][i] V_i   (i < nvec)
-__global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
-{
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.dim * a.ldc) return;
-    const long e = t / a.ldc;
-    const int k = (int)(t - e * a.ldc);
-    const long o = cre(a, e, k);
-    double wr = a.w[o], wi = a.w[o + a.ldc];
-    for (int i = 0; i < nvec; ++i) {
-        const Z h = a.hcur[(long)k * (a.m + 1) + i];
-        const float *vi = a.V + i * a.cvlen;
-        const Z v = {vi[o], vi[o + a.ldc]};
-        const Z p = zmul(h, v);
-        wr -= p.re;
-        wi -= p.im;
-    }
-    a.w[o] = (float)wr;
-    a.w[o + a.ldc] = (float)wi;
-}
-
-// start: beta = ||b|| (hcur[k][0] holds ||b||^2), g = (beta, 0, ...), H = 0, V_0 = b / beta
-__global__ void k_gm_start(GmArgs a)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.ldc) return;
-    const double b = sqrt(a.hcur[(long)k * (a.m + 1)].re);
+    const double b = sqrt(b2);
     a.beta[k] = b;
     a.est[k] = b;
     a.J[k] = 0;
@@ -131,25 +60,10 @@ __global__ void k_gm_start(GmArgs a)
     for (long e = 0; e < (long)(a.m + 1) * a.m; ++e) a.H[(long)k * (a.m + 1) * a.m + e] = {0.0, 0.0};
 }
 
-// V_dst = src * scale[k]
-__global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, float *dst)
-{
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.dim * a.ldc) return;
-    const long e = t / a.ldc;
-    const int k = (int)(t - e * a.ldc);
-    const long o = cre(a, e, k);
-    const double s = a.scale[k];
-    dst[o] = (float)(src[o] * s);
-    dst[o + a.ldc] = (float)(src[o + a.ldc] * s);
-}
-
 // iteration j: ||w|| -> H[j+1][j], the earlier rotations on column j, a new rotation, g,
 // the residual estimate and whether the right-hand side continues; scale = 1 / ||w||
-__global__ void k_gm_givens(GmArgs a, int j)
+__device__ void gm_givens(const GmArgs &a, int k, int j, double nw2)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.ldc) return;
     if (!a.active[k]) {
         a.scale[k] = 0.0;
         return;
@@ -159,7 +73,7 @@ __global__ void k_gm_givens(GmArgs a, int j)
     Z *g = a.g + (long)k * (m + 1);
     double *cs = a.cs + (long)k * m;
     Z *sn = a.sn + (long)k * m;
-    const double nw = sqrt(a.hcur[(long)k * (m + 1)].re);
+    const double nw = sqrt(nw2);
     for (int i = 0; i < j; ++i) {
         const Z x0 = H[i * m + j], x1 = H[(i + 1) * m + j];
         const Z s1 = zmul(sn[i], x1), s0 = zmul({sn[i].re, -sn[i].im}, x0);
@@ -186,6 +100,122 @@ __global__ void k_gm_givens(GmArgs a, int j)
     a.J[k] = j + 1;
     a.active[k] = nw > 0.0 && est > a.tol * a.beta[k];
     a.scale[k] = nw > 0.0 ? 1.0 / nw : 0.0;
+}
+
+// part[i][blk][k] = sum over this block's chunk of entries of conj(X_i) y, for the vectors
+// X_i = X + i * xstride (i = blockIdx.y) and every right-hand side k
+__global__ void __launch_bounds__(DTHR) k_gm_dots(GmArgs a, const float *X, long xstride, const float *y)
+{
+    __shared__ Z red[DROWS][32];
+    const int G = gridDim.x, i = blockIdx.y;
+    const int k = threadIdx.x & 31, row = threadIdx.x >> 5;
+    const long chunk = (a.dim + G - 1) / G, e0 = blockIdx.x * chunk, e1 = e0 + chunk < a.dim ? e0 + chunk : a.dim;
+    const float *xi = X + i * xstride;
+    Z s = {0.0, 0.0};
+    if (k < a.ldc)
+        for (long e = e0 + row; e < e1; e += DROWS) {
+            const long o = cre(a, e, k);
+            const Z xv = {xi[o], xi[o + a.ldc]}, yv = {y[o], y[o + a.ldc]};
+            const Z p = zconjmul(xv, yv);
+            s.re += p.re;
+            s.im += p.im;
+        }
+    red[row][k] = s;
+    __syncthreads();
+    if (row == 0 && k < a.ldc) {
+        Z t = red[0][k];
+        for (int r = 1; r < DROWS; ++r) {
+            t.re += red[r][k].re;
+            t.im += red[r][k].im;
+        }
+        a.part[((long)i * G + blockIdx.x) * a.ldc + k] = t;
+    }
+}
+
+enum GmStep { GM_PROJECT = 1, GM_NORM = 2, GM_START = 3 };
+
+constexpr int FR = 16;  // threads per inner product in k_gm_finish
+
+// h_i[k] = the G partial sums of k_gm_dots added up (thread r of an output's FR threads takes
+// blocks r, r + FR, ... in order; the FR sums are combined by a fixed shuffle tree), then the
+// step that needs them:
+//   GM_PROJECT: hcur[k][i] = h_i, and H[k][i][col] += h_i for the right-hand sides still active
+//   GM_NORM   : (X = y = w) the Givens step of iteration col with ||w||^2
+//   GM_START  : (X = y = b) the start of the iteration with ||b||^2
+__global__ void __launch_bounds__(256) k_gm_finish(GmArgs a, int G, int nvec, int col, int step)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int o = t / FR, r = t - o * FR;
+    const bool ok = o < nvec * a.ldc;
+    const int i = ok ? o / a.ldc : 0, k = ok ? o - i * a.ldc : 0;
+    const Z *pp = a.part + (long)i * G * a.ldc + k;
+    Z s = {0.0, 0.0};
+    if (ok) {
+#pragma unroll 8
+        for (int b = r; b < G; b += FR) {
+            const Z p = pp[(long)b * a.ldc];
+            s.re += p.re;
+            s.im += p.im;
+        }
+    }
+    for (int off = 1; off < FR; off *= 2) {
+        s.re += __shfl_down(s.re, off, FR);
+        s.im += __shfl_down(s.im, off, FR);
+    }
+    if (!ok || r != 0) return;
+    a.hcur[(long)k * (a.m + 1) + i] = s;
+    if (step == GM_PROJECT) {
+        if (a.active[k]) {
+            Z &h = a.H[((long)k * (a.m + 1) + i) * a.m + col];
+            h.re += s.re;
+            h.im += s.im;
+        }
+    } else if (step == GM_NORM) {
+        gm_givens(a, k, col, s.re);
+    } else {
+        gm_start(a, k, s.re);
+    }
+}
+
+// blocks per vector of an inner-product launch over nvec vectors
+int gm_blocks(const GmArgs &a, int nvec)
+{
+    const long want = (a.dim + 4 * DROWS - 1) / (4 * DROWS);  // at least 4 entries per thread
+    return (int)std::max<long>(1, std::min<long>(want, GPART / nvec));
+}
+
+// w -= sum_i hcur[k][i] V_i   (i < nvec)
+__global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.dim * a.ldc) return;
+    const long e = t / a.ldc;
+    const int k = (int)(t - e * a.ldc);
+    const long o = cre(a, e, k);
+    double wr = a.w[o], wi = a.w[o + a.ldc];
+    for (int i = 0; i < nvec; ++i) {
+        const Z h = a.hcur[(long)k * (a.m + 1) + i];
+        const float *vi = a.V + i * a.cvlen;
+        const Z v = {vi[o], vi[o + a.ldc]};
+        const Z p = zmul(h, v);
+        wr -= p.re;
+        wi -= p.im;
+    }
+    a.w[o] = (float)wr;
+    a.w[o + a.ldc] = (float)wi;
+}
+
+// V_dst = src * scale[k]
+__global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, float *dst)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.dim * a.ldc) return;
+    const long e = t / a.ldc;
+    const int k = (int)(t - e * a.ldc);
+    const long o = cre(a, e, k);
+    const double s = a.scale[k];
+    dst[o] = (float)(src[o] * s);
+    dst[o + a.ldc] = (float)(src[o + a.ldc] * s);
 }
 
 // y = H^-1 g (back substitution over the J[k] iterations taken), into hcur
@@ -245,7 +275,6 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
     const int ldc = (n + 3) / 4 * 4;
     const long dim = (long)op->n_agg * 2 * n_tv;
     const long cvlen = dim * 2 * ldc;
-    const int G = (int)std::min<long>(512, std::max<long>(1, (dim + 255) / 256));
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -254,7 +283,7 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
     };
     char *V = take(sizeof(float) * cvlen * (m + 1));
     char *w = take(sizeof(float) * cvlen);
-    char *part = take(sizeof(Z) * (size_t)G * (m + 1) * ldc);
+    char *part = take(sizeof(Z) * (size_t)GPART * ldc);
     char *hcur = take(sizeof(Z) * (size_t)ldc * (m + 1));
     char *H = take(sizeof(Z) * (size_t)ldc * (m + 1) * m);
     char *g = take(sizeof(Z) * (size_t)ldc * (m + 1));
@@ -271,7 +300,6 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
         a->m = m;
         a->dim = dim;
         a->cvlen = cvlen;
-        a->G = G;
         a->V = (float *)V;
         a->w = (float *)w;
         a->part = (Z *)part;
@@ -304,34 +332,26 @@ int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const floa
     const int kb = (a.ldc + 63) / 64;
 #define GM_CHECK(what) \
     if (int rc = hip_check(hipGetLastError(), what)) return rc
+    auto dots = [&](const float *X, long xstride, int nvec, const float *y, int col, int step) {
+        const int G = gm_blocks(a, nvec);
+        hipLaunchKernelGGL(k_gm_dots, dim3(G, nvec), dim3(DTHR), 0, st, a, X, xstride, y);
+        if (int rc = hip_check(hipGetLastError(), "k_gm_dots launch")) return rc;
+        hipLaunchKernelGGL(k_gm_finish, dim3((nvec * a.ldc * FR + 255) / 256), dim3(256), 0, st, a, G, nvec, col, step);
+        return hip_check(hipGetLastError(), "k_gm_finish launch");
+    };
     // beta, V_0
-    hipLaunchKernelGGL(k_gm_dots, dim3(a.G, 1), dim3(GTHR), 0, st, a, b, 0L, 1, b);
-    GM_CHECK("k_gm_dots launch");
-    hipLaunchKernelGGL(k_gm_dots_finish, dim3((a.ldc + 63) / 64), dim3(64), 0, st, a, 1, 0, 0);
-    GM_CHECK("k_gm_dots_finish launch");
-    hipLaunchKernelGGL(k_gm_start, dim3(kb), dim3(64), 0, st, a);
-    GM_CHECK("k_gm_start launch");
+    if (int rc = dots(b, 0L, 1, b, 0, GM_START)) return rc;
     hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, b, a.V);
     GM_CHECK("k_gm_scale launch");
     for (int j = 0; j < m; ++j) {
         float *vj = a.V + (long)j * a.cvlen;
         if (int rc = launch_coarse_apply(op, Dc, n_tv, vj, a.w, n, st)) return rc;
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(k_gm_dots, dim3(a.G, j + 1), dim3(GTHR), 0, st, a, (const float *)a.V, a.cvlen, j + 1,
-                               (const float *)a.w);
-            GM_CHECK("k_gm_dots launch");
-            hipLaunchKernelGGL(k_gm_dots_finish, dim3(((j + 1) * a.ldc + 63) / 64), dim3(64), 0, st, a, j + 1, j, 1);
-            GM_CHECK("k_gm_dots_finish launch");
+            if (int rc = dots(a.V, a.cvlen, j + 1, a.w, j, GM_PROJECT)) return rc;
             hipLaunchKernelGGL(k_gm_axpy, dim3(eb), dim3(GTHR), 0, st, a, j + 1);
             GM_CHECK("k_gm_axpy launch");
         }
-        hipLaunchKernelGGL(k_gm_dots, dim3(a.G, 1), dim3(GTHR), 0, st, a, (const float *)a.w, 0L, 1,
-                           (const float *)a.w);
-        GM_CHECK("k_gm_dots launch");
-        hipLaunchKernelGGL(k_gm_dots_finish, dim3((a.ldc + 63) / 64), dim3(64), 0, st, a, 1, 0, 0);
-        GM_CHECK("k_gm_dots_finish launch");
-        hipLaunchKernelGGL(k_gm_givens, dim3(kb), dim3(64), 0, st, a, j);
-        GM_CHECK("k_gm_givens launch");
+        if (int rc = dots(a.w, 0L, 1, a.w, j, GM_NORM)) return rc;
         hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, (const float *)a.w, a.V + (long)(j + 1) * a.cvlen);
         GM_CHECK("k_gm_scale launch");
     }

@@ -235,9 +235,13 @@ __global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
-// coarse apply: one workgroup per coarse site.  Output tiles: rows (2N dofs) x columns
-// (right-hand sides), at most 4 x 2, two per wavefront; K runs over the 9 blocks and their
-// 2N columns.
+// coarse apply: one workgroup per (coarse site, 16-row tile of the 2N output rows).  The
+// nine blocks are split over three groups of wavefronts (directions d = g, g + 3, g + 6);
+// each group has one wavefront per 16-column tile of right-hand sides.  For each direction
+// the group copies the block's 16-row slab (contiguous in D_c) into LDS with 16-byte loads
+// and issues all its loads of the neighbour's vector (2N rows x 16 right-hand sides) before
+// the KS = ceil(2N / 4) matrix-core steps.  The three partial tiles are summed through LDS in
+// the order g = 0, 1, 2.
 // ---------------------------------------------------------------------------------------
 struct CApplyArgs {
     int na[4];
@@ -247,68 +251,98 @@ struct CApplyArgs {
     float *yco;
 };
 
-__global__ void __launch_bounds__(TTHR) k_coarse_apply(CApplyArgs a)
+constexpr int CA_GROUPS = 3;
+constexpr int CA_MAXTHR = 64 * CA_GROUPS * 2;  // two right-hand-side tiles (n <= 32)
+
+template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CApplyArgs a)
 {
-    const int i = blockIdx.x;
+    __shared__ f4 part[CA_GROUPS - 1][2][2][64];  // [g - 1][tk][re, im][lane]
+    __shared__ float slab[CA_GROUPS][16 * 130];  // 16 rows of 2N complex, row stride 4N + 2 floats
+    const int N2 = 2 * a.N, TR = (N2 + 15) / 16, TK = (a.n + 15) / 16, RS = 2 * N2 + 2;
+    const int i = blockIdx.x / TR, tr = blockIdx.x - i * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int N2 = 2 * a.N;
-    const int TR = (N2 + 15) / 16, TK = (a.n + 15) / 16, ntile = TR * TK, KS = (N2 + 3) / 4;
+    const int g = wave / TK, tk = wave - g * TK;
     int c[4], r = i;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         c[m] = r % a.na[m];
         r /= a.na[m];
     }
-    f4 dr[2], di[2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) dr[m] = di[m] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int d = 0; d < 9; ++d) {
+    const int row = 16 * tr + (lane & 15), k = 16 * tk + (lane & 15);
+    const int rows_here = N2 - 16 * tr < 16 ? N2 - 16 * tr : 16;
+    const bool rok = row < N2, kok = k < a.n;
+    f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
+    float *sl = slab[g];
+    for (int d = g; d < 9; d += CA_GROUPS) {
         int cn[4] = {c[0], c[1], c[2], c[3]};
         if (d >= 1 && d <= 4) cn[d - 1] = (cn[d - 1] + 1) % a.na[d - 1];
         if (d >= 5) cn[d - 5] = (cn[d - 5] - 1 + a.na[d - 5]) % a.na[d - 5];
         const int j = cn[0] + a.na[0] * (cn[1] + a.na[1] * (cn[2] + a.na[2] * cn[3]));
-        const float *blk = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
+        const float *blk = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2 + (size_t)16 * tr * N2 * 2;
         const float *yj = a.yc + (size_t)j * N2 * 2 * a.ldc;
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const int tile = wave + TNW * m;
-            if (tile >= ntile) break;
-            const int tr = tile / TK, tk = tile - tr * TK;
-            const int row = 16 * tr + (lane & 15), k = 16 * tk + (lane & 15);
-            const bool rok = row < N2, kok = k < a.n;
-            for (int ks = 0; ks < KS; ++ks) {
-                const int col = 4 * ks + (lane >> 4);  // K index: the block's column (coarse dof)
-                const bool aok = rok && col < N2, bok = kok && col < N2;
-                const size_t ia = aok ? ((size_t)row * N2 + col) * 2 : 0;
-                const size_t ib = bok ? (size_t)(2 * col) * a.ldc + k : 0;
-                const float a0 = blk[ia], a1 = blk[aok ? ia + 1 : 0];
-                const float b0 = yj[ib], b1 = yj[bok ? ib + a.ldc : 0];
-                const float xr = aok ? a0 : 0.f, xi = aok ? a1 : 0.f;
-                const float yr = bok ? b0 : 0.f, yi = bok ? b1 : 0.f;
-                // D y = (xr yr - xi yi) + i (xr yi + xi yr)
-                dr[m] = mfma32(xr, yr, dr[m]);
-                dr[m] = mfma32(-xi, yi, dr[m]);
-                di[m] = mfma32(xr, yi, di[m]);
-                di[m] = mfma32(xi, yr, di[m]);
-            }
+        // the 16-row slab of the block (contiguous) into LDS
+        const int nq = rows_here * a.N;  // float4 per row: 2 N2 / 4 = N
+        for (int q = tk * 64 + lane; q < nq; q += 64 * TK) {
+            const int rr = q / a.N, c4 = q - rr * a.N;
+            const float4 v = ((const float4 *)blk)[q];
+            *(float2 *)&sl[rr * RS + 4 * c4] = make_float2(v.x, v.y);
+            *(float2 *)&sl[rr * RS + 4 * c4 + 2] = make_float2(v.z, v.w);
         }
+        float br[KS], bi[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int col = 4 * ks + (lane >> 4);
+            const bool bok = kok && col < N2;
+            const size_t ib = bok ? (size_t)(2 * col) * a.ldc + k : 0;
+            const float b0 = yj[ib], b1 = yj[bok ? ib + a.ldc : 0];
+            br[ks] = bok ? b0 : 0.f;
+            bi[ks] = bok ? b1 : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int col = 4 * ks + (lane >> 4);
+            const bool aok = rok && col < N2;
+            const float2 v = *(const float2 *)&sl[(aok ? (lane & 15) * RS + 2 * col : 0)];
+            const float xr = aok ? v.x : 0.f, xi = aok ? v.y : 0.f;
+            dr = mfma32(xr, br[ks], dr);
+            dr = mfma32(-xi, bi[ks], dr);
+            di = mfma32(xr, bi[ks], di);
+            di = mfma32(xi, br[ks], di);
+        }
+        __syncthreads();
+    }
+    if (g > 0) {
+        part[g - 1][tk][0][lane] = dr;
+        part[g - 1][tk][1][lane] = di;
+    }
+    __syncthreads();
+    if (g > 0) return;
+#pragma unroll
+    for (int q = 0; q < CA_GROUPS - 1; ++q) {
+        dr += part[q][tk][0][lane];
+        di += part[q][tk][1][lane];
     }
     float *out = a.yco + (size_t)i * N2 * 2 * a.ldc;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const int tile = wave + TNW * m;
-        if (tile >= ntile) break;
-        const int tr = tile / TK, tk = tile - tr * TK;
-        const int k = 16 * tk + (lane & 15);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = 16 * tr + 4 * (lane >> 4) + q;
-            if (row < N2 && k < a.ldc) {
-                out[(size_t)(2 * row) * a.ldc + k] = k < a.n ? dr[m][q] : 0.f;
-                out[(size_t)(2 * row + 1) * a.ldc + k] = k < a.n ? di[m][q] : 0.f;
-            }
+    for (int q = 0; q < 4; ++q) {
+        const int orow = 16 * tr + 4 * (lane >> 4) + q;
+        if (orow < N2 && k < a.ldc) {
+            out[(size_t)(2 * orow) * a.ldc + k] = kok ? dr[q] : 0.f;
+            out[(size_t)(2 * orow + 1) * a.ldc + k] = kok ? di[q] : 0.f;
         }
     }
+}
+
+// KS = ceil(2N / 4) = 1 .. 16 (n_tv <= 32)
+template <int KS> int coarse_apply_ks(const CApplyArgs &a, int ks, hipStream_t st)
+{
+    if constexpr (KS < 16) {
+        if (ks > KS) return coarse_apply_ks<KS + 1>(a, ks, st);
+    }
+    const int TR = (2 * a.N + 15) / 16, TK = (a.n + 15) / 16;
+    hipLaunchKernelGGL(k_coarse_apply<KS>, dim3(a.Vc * TR), dim3(64 * CA_GROUPS * TK), 0, st, a);
+    return hip_check(hipGetLastError(), "k_coarse_apply launch");
 }
 
 TransArgs trans_args(const mrhs_op *op, int n_tv, int n)
@@ -388,6 +422,6 @@ int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const floa
     a.Dc = Dc;
     a.yc = yc;
     a.yco = yco;
-    hipLaunchKernelGGL(k_coarse_apply, dim3(a.Vc), dim3(TTHR), 0, st, a);
-    return hip_check(hipGetLastError(), "k_coarse_apply launch");
+    if (n_tv < 1 || n_tv > 32 || n < 1 || n > 32) return set_error(MRHS_EUNSUPPORTED, "coarse apply: n_tv and n must be 1..32");
+    return coarse_apply_ks<1>(a, (2 * n_tv + 3) / 4, st);
 }
