@@ -56,6 +56,8 @@ def lib():
             "oracle_sap_from": (i, [p, p, p, p, p, p, i, i, i]),
             "oracle_coarse_gmres": (None, [p, p, p, i, p, p, i, i, ctypes.c_double, p, p]),
             "oracle_coarse_op": (None, [p, p, p, p, p, i, p, p, l]),
+            "oracle_eo_block": (i, [p, p, p, p, p, l, p, i, p, p]),
+            "oracle_sap_from_eo": (i, [p, p, p, p, p, p, p, i, i, i]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -136,11 +138,43 @@ def mr(L, b, U, A, j, r, n_mr):
     return e, norms
 
 
-def sap(L, b, U, A, rhs, n_sap, n_mr, x0=None):
+def clover_inverse(A):
+    """A(x)^-1 per site, [V][12][12] (numpy's inverse: the even-odd block solver's A_oo^-1)."""
+    return np.ascontiguousarray(np.linalg.inv(_c128(A)))
+
+
+def eo_block(L, b, U, A, j, r, n_mr, Ainv=None):
+    """The even-odd block solve of D_j e = r on block j (Schur complement over the block's
+    even sites, n_mr MR steps, then the odd sites): returns (e, ||rho_e|| history)."""
+    L, b = _ext(L), _ext(b)
+    r, n = _vecs(r, L)
+    assert n == 1
+    if Ainv is None:
+        Ainv = clover_inverse(A)
+    e = np.zeros_like(r)
+    norms = np.zeros(n_mr + 1)
+    rc = lib().oracle_eo_block(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(_c128(Ainv)), int(j), _ptr(r),
+                               int(n_mr), _ptr(e), _ptr(norms))
+    if rc != 0:
+        raise ValueError("oracle_eo_block: block extents must be even")
+    return e, norms
+
+
+def sap(L, b, U, A, rhs, n_sap, n_mr, x0=None, eo=False, Ainv=None):
     """x = SAP(rhs) per vector, from a zero start (the initial setup phase of Sec. 2) or from
-    the starting guess x0 (the refinement phase, Alg. 1 and 2)."""
+    the starting guess x0 (the refinement phase, Alg. 1 and 2); eo=True: the even-odd block
+    solver (eo_block) instead of plain MR."""
     L, b = _ext(L), _ext(b)
     rhs, n = _vecs(rhs, L)
+    if eo:
+        if Ainv is None:
+            Ainv = clover_inverse(A)
+        x = np.zeros_like(rhs) if x0 is None else np.array(_c128(x0), copy=True).reshape(rhs.shape)
+        rc = lib().oracle_sap_from_eo(_ptr(L), _ptr(b), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(_c128(Ainv)), _ptr(rhs),
+                                      _ptr(x), n, int(n_sap), int(n_mr))
+        if rc != 0:
+            raise ValueError("oracle_sap_from_eo: block extents must be even")
+        return x
     if x0 is None:
         x = np.zeros_like(rhs)
         fn = lib().oracle_sap

@@ -29,7 +29,9 @@
  *   - SAP: red-black multiplicative Schwarz over lattice blocks, the residual
  *     recomputed before each colour, red (even block-coordinate sum) first;
  *   - block solver: plain minimal residual with a fixed number of steps, step
- *     length set to 0 when the block residual's image is exactly zero;
+ *     length set to 0 when the block residual's image is exactly zero; or (the
+ *     even-odd variant, DD-alpha-AMG's block solver) the same steps on the block's
+ *     Schur complement over its even sites, then the odd sites from the even ones;
  *   - Gram-Schmidt: the unique thin QR factor with positive real diagonal,
  *     computed by modified Gram-Schmidt with one re-orthogonalisation pass.
  *
@@ -429,6 +431,147 @@ void oracle_mr(const int *L, const int *b, const double *U_, const double *A_, l
 }
 
 /* ------------------------------------------------------------------------ */
+/* Even-odd preconditioned block solve                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Parity of a block's k-th site: the sum of its block-local coordinates mod 2.  With every
+ * block extent even, each hop inside a block joins sites of opposite parity, so in (even,
+ * odd) order the block operator is D_j = [[A_ee, H_eo], [H_oe, A_oo]]: A the site-diagonal
+ * clover term, H the hops inside the block.  Then H_oe v_e is the odd part of D_j (v_e, 0)
+ * and H_eo u_o the even part of D_j (0, u_o). */
+static int local_parity(const int *b, long k)
+{
+    int y[4];
+    site_coords(b, k, y);
+    return (y[0] + y[1] + y[2] + y[3]) & 1;
+}
+
+/* out_k = M(x_k) in_k at the block's sites of parity p, 0 at the others (M: [V][12][12]) */
+static void site_mat(const int *L, const int *b, long j, const cplx *M, int p, const cplx *in, cplx *out)
+{
+    long Vb = (long)b[0] * b[1] * b[2] * b[3];
+    for (long k = 0; k < Vb; ++k) {
+        cplx *o = out + 12 * k;
+        if (local_parity(b, k) != p) {
+            for (int r = 0; r < 12; ++r) o[r] = 0;
+            continue;
+        }
+        const cplx *m = M + block_site(L, b, j, k) * 144, *v = in + 12 * k;
+        for (int r = 0; r < 12; ++r) {
+            cplx acc = 0;
+            for (int c = 0; c < 12; ++c) acc += m[r * 12 + c] * v[c];
+            o[r] = acc;
+        }
+    }
+}
+
+/* keep the parity-p part of a block-local vector, zero the rest */
+static void keep_parity(const int *b, int p, const cplx *in, cplx *out)
+{
+    long Vb = (long)b[0] * b[1] * b[2] * b[3];
+    for (long k = 0; k < Vb; ++k)
+        for (int r = 0; r < 12; ++r) out[12 * k + r] = local_parity(b, k) == p ? in[12 * k + r] : 0;
+}
+
+/* q = S v, the Schur complement S = A_ee - H_eo A_oo^-1 H_oe on the even part of v; the odd
+ * part of q is zero.  t1, t2: block-local scratch. */
+static void schur_op(const int *L, const int *b, const cplx *U, const cplx *A, const cplx *Ainv, long j,
+                     const cplx *v, cplx *q, cplx *t1, cplx *t2)
+{
+    long n = 12L * b[0] * b[1] * b[2] * b[3];
+    keep_parity(b, 0, v, t1);
+    block_op(L, b, U, A, j, t1, t2);      /* t2 = (A_ee v_e, H_oe v_e) */
+    site_mat(L, b, j, Ainv, 1, t2, t1);   /* t1 = (0, A_oo^-1 H_oe v_e) */
+    block_op(L, b, U, A, j, t1, q);       /* q_e = H_eo A_oo^-1 H_oe v_e */
+    for (long i = 0; i < n; ++i) q[i] = t2[i] - q[i];
+    keep_parity(b, 0, q, q);
+}
+
+/* D_j e = r on block j by the Schur complement:
+ *   rhat_e = r_e - H_eo A_oo^-1 r_o,
+ *   n_mr minimal-residual steps on S e_e = rhat_e from e_e = 0 (as in mr_block, S for D_j),
+ *   e_o = A_oo^-1 (r_o - H_oe e_e).
+ * rho_norms (nullable) receives ||rho_e|| before each step and after the last. */
+static void eo_block(const int *L, const int *b, const cplx *U, const cplx *A, const cplx *Ainv, long j,
+                     const cplx *r, int n_mr, cplx *e, double *rho_norms)
+{
+    long n = 12L * b[0] * b[1] * b[2] * b[3];
+    cplx *rho = malloc(n * sizeof(cplx)), *q = malloc(n * sizeof(cplx));
+    cplx *t1 = malloc(n * sizeof(cplx)), *t2 = malloc(n * sizeof(cplx));
+    site_mat(L, b, j, Ainv, 1, r, t1);   /* (0, A_oo^-1 r_o) */
+    block_op(L, b, U, A, j, t1, t2);     /* even part: H_eo A_oo^-1 r_o */
+    for (long i = 0; i < n; ++i) rho[i] = r[i] - t2[i];
+    keep_parity(b, 0, rho, rho);
+    for (long i = 0; i < n; ++i) e[i] = 0;
+    for (int it = 0; it < n_mr; ++it) {
+        if (rho_norms) {
+            double s = 0;
+            for (long i = 0; i < n; ++i) s += creal(conj(rho[i]) * rho[i]);
+            rho_norms[it] = sqrt(s);
+        }
+        schur_op(L, b, U, A, Ainv, j, rho, q, t1, t2);
+        double qq = 0;
+        cplx qr = 0;
+        for (long i = 0; i < n; ++i) {
+            qq += creal(conj(q[i]) * q[i]);
+            qr += conj(q[i]) * rho[i];
+        }
+        cplx alpha = qq > 0 ? qr / qq : 0;
+        for (long i = 0; i < n; ++i) {
+            e[i] += alpha * rho[i];
+            rho[i] -= alpha * q[i];
+        }
+    }
+    if (rho_norms) {
+        double s = 0;
+        for (long i = 0; i < n; ++i) s += creal(conj(rho[i]) * rho[i]);
+        rho_norms[n_mr] = sqrt(s);
+    }
+    /* odd sites: (D_j (e_e, 0))_o = H_oe e_e */
+    block_op(L, b, U, A, j, e, t2);
+    for (long i = 0; i < n; ++i) t1[i] = r[i] - t2[i];
+    site_mat(L, b, j, Ainv, 1, t1, t2);
+    for (long i = 0; i < n; ++i) e[i] += t2[i];
+    free(rho);
+    free(q);
+    free(t1);
+    free(t2);
+}
+
+static int even_extents(const int *b)
+{
+    for (int mu = 0; mu < 4; ++mu)
+        if (b[mu] % 2) return 0;
+    return 1;
+}
+
+/* eo_block on block j for one full-lattice residual r; e (full lattice) receives the block
+ * solution on block j and zero elsewhere.  Ainv: [V][12][12], the inverse of A per site.
+ * Returns -2 if a block extent is odd. */
+int oracle_eo_block(const int *L, const int *b, const double *U_, const double *A_, const double *Ainv_, long j,
+                    const double *r_, int n_mr, double *e_, double *rho_norms)
+{
+    if (!even_extents(b)) return -2;
+    const cplx *U = (const cplx *)U_, *A = (const cplx *)A_, *Ainv = (const cplx *)Ainv_, *r = (const cplx *)r_;
+    cplx *e = (cplx *)e_;
+    long V = volume(L), Vb = (long)b[0] * b[1] * b[2] * b[3];
+    cplx *rl = malloc(12 * Vb * sizeof(cplx)), *el = malloc(12 * Vb * sizeof(cplx));
+    for (long k = 0; k < Vb; ++k) {
+        long x = block_site(L, b, j, k);
+        for (int c = 0; c < 12; ++c) rl[12 * k + c] = r[12 * x + c];
+    }
+    eo_block(L, b, U, A, Ainv, j, rl, n_mr, el, rho_norms);
+    for (long i = 0; i < 12 * V; ++i) e[i] = 0;
+    for (long k = 0; k < Vb; ++k) {
+        long x = block_site(L, b, j, k);
+        for (int c = 0; c < 12; ++c) e[12 * x + c] = el[12 * k + c];
+    }
+    free(rl);
+    free(el);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Schwarz alternating procedure                                             */
 /* ------------------------------------------------------------------------ */
 
@@ -438,10 +581,10 @@ void oracle_mr(const int *L, const int *b, const double *U_, const double *A_, l
 /* SAP from a given starting guess: x_io holds x0 on entry and the result on exit (the
  * refinement phase of the setup, Alg. 1 and 2: the smoother starts from the coarse-grid
  * correction).  oracle_sap below is the start from zero of the initial phase. */
-int oracle_sap_from(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_,
-                    double *x_io_, int n_rhs, int n_sap, int n_mr)
+static int sap_from(const int *L, const int *b, const double *U_, const double *A_, const double *Ainv_,
+                    const double *b_in_, double *x_io_, int n_rhs, int n_sap, int n_mr)
 {
-    const cplx *U = (const cplx *)U_, *A = (const cplx *)A_;
+    const cplx *U = (const cplx *)U_, *A = (const cplx *)A_, *Ainv = (const cplx *)Ainv_;
     long V = volume(L), Vb = (long)b[0] * b[1] * b[2] * b[3];
     int nb[4];
     for (int mu = 0; mu < 4; ++mu)
@@ -469,7 +612,8 @@ int oracle_sap_from(const int *L, const int *b, const double *U_, const double *
                         long xs = block_site(L, b, j, kk);
                         for (int c = 0; c < 12; ++c) rl[12 * kk + c] = r[12 * xs + c];
                     }
-                    mr_block(L, b, U, A, j, rl, n_mr, el, NULL);
+                    if (Ainv) eo_block(L, b, U, A, Ainv, j, rl, n_mr, el, NULL);
+                    else mr_block(L, b, U, A, j, rl, n_mr, el, NULL);
                     for (long kk = 0; kk < Vb; ++kk) {
                         long xs = block_site(L, b, j, kk);
                         for (int c = 0; c < 12; ++c) x[12 * xs + c] += el[12 * kk + c];
@@ -481,6 +625,20 @@ int oracle_sap_from(const int *L, const int *b, const double *U_, const double *
     }
     free(r);
     return 0;
+}
+
+int oracle_sap_from(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_,
+                    double *x_io_, int n_rhs, int n_sap, int n_mr)
+{
+    return sap_from(L, b, U_, A_, NULL, b_in_, x_io_, n_rhs, n_sap, n_mr);
+}
+
+/* SAP from a starting guess with the even-odd block solver (eo_block); Ainv: [V][12][12] */
+int oracle_sap_from_eo(const int *L, const int *b, const double *U_, const double *A_, const double *Ainv_,
+                       const double *b_in_, double *x_io_, int n_rhs, int n_sap, int n_mr)
+{
+    if (!even_extents(b)) return -2;
+    return sap_from(L, b, U_, A_, Ainv_, b_in_, x_io_, n_rhs, n_sap, n_mr);
 }
 
 int oracle_sap(const int *L, const int *b, const double *U_, const double *A_, const double *b_in_, double *x_out_,
