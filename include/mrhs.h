@@ -220,6 +220,23 @@ int sap_smooth_mrhs_batched(mrhs_op *const *ops, int32_t n_inst, const void *con
                             void *stream);
 size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const int32_t *n_rhs);
 
+/* Block solver of the SAP (every SAP entry point of the op, the refinement pass included).
+ *   MRHS_BLOCK_MR    (default): n_mr minimal-residual steps on D_j from zero;
+ *   MRHS_BLOCK_EO_MR : DD-alpha-AMG's even-odd preconditioned block solve.  A block's sites
+ *     are split by the parity of their block-local coordinate sum (every block extent must
+ *     be even, so each hop inside a block joins opposite parities): D_j = [[A_ee, H_eo],
+ *     [H_oe, A_oo]] with A the clover term and H the hops inside the block.  n_mr
+ *     minimal-residual steps are taken on the Schur complement S = A_ee - H_eo A_oo^-1 H_oe
+ *     for S e_e = r_e - H_eo A_oo^-1 r_o from zero, then e_o = A_oo^-1 (r_o - H_oe e_e).
+ * The first switch to MRHS_BLOCK_EO_MR computes A^-1 per site (FP64 Gauss-Jordan with
+ * partial pivoting on each 6x6 block, kept by the op, 576 B per site, +288 B with FP32
+ * fields) and synchronises the stream.  Errors: EUNSUPPORTED for an odd block extent,
+ * EINVAL for an unknown solver or a clover block without a usable pivot (the op keeps its
+ * previous solver). */
+#define MRHS_BLOCK_MR 0
+#define MRHS_BLOCK_EO_MR 1
+int mrhs_set_block_solver(mrhs_op *op, int32_t solver, void *stream);
+
 /* Execution tiles (right-hand sides per workgroup) of the SAP and stencil kernels; 0 keeps
  * the current choice.  A tile must divide the op's short length and fit the block. */
 int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile);

@@ -78,7 +78,7 @@ void free_op(mrhs_op *op)
 {
     if (!op) return;
     void *ptrs[] = {op->links64, op->clover64, op->links32, op->clover32, op->blk_coords, op->loc_coords,
-                    op->colour_blocks, op->agg_sites};
+                    op->colour_blocks, op->agg_sites, op->cloverinv64, op->cloverinv32, op->eo_sites};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -536,6 +536,65 @@ int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile)
             return set_error(MRHS_EINVAL, "stencil tile must be 1, 2 or 4, divide S and fit the block");
         op->dirac_tile = dirac_tile;
     }
+    return MRHS_OK;
+}
+
+int mrhs_set_block_solver(mrhs_op *op, int32_t solver, void *stream)
+{
+    if (int rc = check_op(op)) return rc;
+    if (solver == MRHS_BLOCK_MR) {
+        op->block_solver = MRHS_BLOCK_MR;
+        return MRHS_OK;
+    }
+    if (solver != MRHS_BLOCK_EO_MR) return set_error(MRHS_EINVAL, "unknown block solver");
+    for (int mu = 0; mu < 4; ++mu)
+        if (op->k.b[mu] % 2) return set_error(MRHS_EUNSUPPORTED, "the even-odd block solver needs even block extents");
+    if (!op->cloverinv64) {
+        const long V = op->k.V;
+        const int Vb = op->k.Vb;
+        std::vector<int32_t> order;
+        for (int p = 0; p < 2; ++p)
+            for (int off = 0; off < Vb; ++off) {
+                int q = off, par = 0;
+                for (int mu = 0; mu < 4; ++mu) {
+                    par += q % op->k.b[mu];
+                    q /= op->k.b[mu];
+                }
+                if ((par & 1) == p) order.push_back(off);
+            }
+        hipStream_t st = (hipStream_t)stream;
+        double *inv64 = nullptr;
+        float *inv32 = nullptr;
+        int32_t *eo = nullptr;
+        int *bad = nullptr;
+        int rc = hip_check(hipMalloc((void **)&inv64, sizeof(double) * 72 * V), "hipMalloc cloverinv64");
+        if (!rc && op->clover32) rc = hip_check(hipMalloc((void **)&inv32, sizeof(float) * 72 * V), "hipMalloc cloverinv32");
+        if (!rc) rc = hip_check(hipMalloc((void **)&eo, sizeof(int32_t) * Vb), "hipMalloc eo_sites");
+        if (!rc) rc = hip_check(hipMalloc((void **)&bad, sizeof(int)), "hipMalloc flag");
+        if (!rc) rc = hip_check(hipMemcpyAsync(eo, order.data(), sizeof(int32_t) * Vb, hipMemcpyHostToDevice, st), "copy");
+        if (!rc) rc = hip_check(hipMemsetAsync(bad, 0, sizeof(int), st), "hipMemsetAsync flag");
+        if (!rc) {
+            op->cloverinv64 = inv64;
+            op->cloverinv32 = inv32;
+            rc = launch_clover_inverse(op, bad, st);
+        }
+        int hbad = 0;
+        if (!rc) rc = hip_check(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
+        if (!rc) rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize(set_block_solver)");
+        if (bad) (void)hipFree(bad);
+        if (!rc && hbad) rc = set_error(MRHS_EINVAL, "the clover term has a singular 6x6 block");
+        if (rc) {
+            (void)hipStreamSynchronize(st);
+            if (inv64) (void)hipFree(inv64);
+            if (inv32) (void)hipFree(inv32);
+            if (eo) (void)hipFree(eo);
+            op->cloverinv64 = nullptr;
+            op->cloverinv32 = nullptr;
+            return rc;
+        }
+        op->eo_sites = eo;
+    }
+    op->block_solver = MRHS_BLOCK_EO_MR;
     return MRHS_OK;
 }
 

@@ -235,6 +235,85 @@ __global__ void k_unpack(KGeo g, const Ts *__restrict__ nat, double *__restrict_
     }
 }
 
+// One Hermitian 6x6 block of the clover term per thread (site, half): the inverse by
+// Gauss-Jordan elimination with partial pivoting in FP64, written back in the same packed
+// form (real diagonal, then the upper triangle (a, b), a < b, row by row; the stored
+// off-diagonal element is the mean of M^-1[a][b] and conj(M^-1[b][a])).
+__global__ void k_clover_inverse(const double *__restrict__ clover, double *__restrict__ inv, long V,
+                                 int *__restrict__ bad)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * V) return;
+    const double *c = clover + t * 36;
+    double ar[6][12], ai[6][12];  // [M | I]
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 12; ++j) {
+            ar[i][j] = j == i + 6 ? 1.0 : 0.0;
+            ai[i][j] = 0.0;
+        }
+    for (int i = 0; i < 6; ++i) ar[i][i] = c[i];
+    int kk = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j, ++kk) {
+            ar[i][j] = c[6 + 2 * kk];
+            ai[i][j] = c[7 + 2 * kk];
+            ar[j][i] = c[6 + 2 * kk];
+            ai[j][i] = -c[7 + 2 * kk];
+        }
+    bool ok = true;
+    for (int col = 0; col < 6; ++col) {
+        int p = col;
+        double best = ar[col][col] * ar[col][col] + ai[col][col] * ai[col][col];
+        for (int i = col + 1; i < 6; ++i) {
+            const double m = ar[i][col] * ar[i][col] + ai[i][col] * ai[i][col];
+            if (m > best) {
+                best = m;
+                p = i;
+            }
+        }
+        if (!(best > 0.0) || !isfinite(best)) {
+            ok = false;
+            break;
+        }
+        if (p != col)
+            for (int j = 0; j < 12; ++j) {
+                double tr = ar[col][j], ti = ai[col][j];
+                ar[col][j] = ar[p][j];
+                ai[col][j] = ai[p][j];
+                ar[p][j] = tr;
+                ai[p][j] = ti;
+            }
+        // row col /= pivot
+        const double pr = ar[col][col] / best, pi = -ai[col][col] / best;  // 1 / pivot
+        for (int j = 0; j < 12; ++j) {
+            const double xr = ar[col][j], xi = ai[col][j];
+            ar[col][j] = xr * pr - xi * pi;
+            ai[col][j] = xr * pi + xi * pr;
+        }
+        for (int i = 0; i < 6; ++i) {
+            if (i == col) continue;
+            const double fr = ar[i][col], fi = ai[i][col];
+            for (int j = 0; j < 12; ++j) {
+                ar[i][j] -= fr * ar[col][j] - fi * ai[col][j];
+                ai[i][j] -= fr * ai[col][j] + fi * ar[col][j];
+            }
+        }
+    }
+    double *o = inv + t * 36;
+    if (!ok) {
+        atomicOr(bad, 1);
+        for (int i = 0; i < 36; ++i) o[i] = 0.0;
+        return;
+    }
+    for (int i = 0; i < 6; ++i) o[i] = ar[i][i + 6];
+    kk = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 6; ++j, ++kk) {
+            o[6 + 2 * kk] = 0.5 * (ar[i][j + 6] + ar[j][i + 6]);
+            o[7 + 2 * kk] = 0.5 * (ai[i][j + 6] - ai[j][i + 6]);
+        }
+}
+
 int grid_for(long n, int threads)
 {
     long b = (n + threads - 1) / threads;
@@ -254,6 +333,20 @@ int launch_build_fields(mrhs_op *op, const double *links_canon, double m0, doubl
         long nl = 4L * 18 * g.V, nc = 72L * g.V;
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nl, 256)), dim3(256), 0, st, op->links64, op->links32, nl);
         hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nc, 256)), dim3(256), 0, st, op->clover64, op->clover32, nc);
+        if (int rc = hip_check(hipGetLastError(), "k_to_f32 launch")) return rc;
+    }
+    return MRHS_OK;
+}
+
+int launch_clover_inverse(mrhs_op *op, int *bad, hipStream_t st)
+{
+    const long V = op->k.V;
+    hipLaunchKernelGGL(k_clover_inverse, dim3((unsigned)((2 * V + 127) / 128)), dim3(128), 0, st, op->clover64,
+                       op->cloverinv64, V, bad);
+    if (int rc = hip_check(hipGetLastError(), "k_clover_inverse launch")) return rc;
+    if (op->cloverinv32) {
+        const long nc = 72L * V;
+        hipLaunchKernelGGL(k_to_f32, dim3(grid_for(nc, 256)), dim3(256), 0, st, op->cloverinv64, op->cloverinv32, nc);
         if (int rc = hip_check(hipGetLastError(), "k_to_f32 launch")) return rc;
     }
     return MRHS_OK;

@@ -49,6 +49,13 @@ struct mrhs_op {
     bool odd_blocks;                 // some direction has an odd number (> 1) of blocks
     int sap_tile, dirac_tile;
     size_t max_lds;
+    // SAP block solver (mrhs_set_block_solver).  For the even-odd one: A^-1 per site in the
+    // clover layout (two Hermitian 6x6 blocks) and the block-local offsets in parity order,
+    // the Vb / 2 even sites first.
+    int block_solver = 0;
+    double *cloverinv64 = nullptr;
+    float *cloverinv32 = nullptr;
+    int32_t *eo_sites = nullptr;  // [Vb]
 };
 
 // error reporting (abi.hip)

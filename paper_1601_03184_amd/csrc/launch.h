@@ -4,6 +4,9 @@
 
 #include "internal.h"
 
+// A^-1 of the op's clover term per site (FP64, and FP32 when the op has FP32 fields);
+// *bad (device) is set to 1 where a 6x6 block has no usable pivot
+int launch_clover_inverse(mrhs_op *op, int *bad, hipStream_t st);
 int launch_build_fields(mrhs_op *op, const double *links_canon, double m0, double csw, hipStream_t st);
 int launch_pack(const mrhs_op *op, const double *canon, void *native, int dtype, int n_rhs, int *flag, hipStream_t st);
 int launch_unpack(const mrhs_op *op, const void *native, int dtype, double *canon, int n_rhs, hipStream_t st);

@@ -12,6 +12,8 @@
 //      and one LDS exchange, and the correction e kept in registers,
 //   3. writes x|_j (+)= e.
 // The links and clover of a site are loaded once per stencil for all T lanes of the site.
+// With the even-odd block solver (k_sap_batched_eo) step 2 runs on the block's Schur
+// complement over its even sites instead (sap_block_eo).
 #include <algorithm>
 
 #include "launch.h"
@@ -32,6 +34,11 @@ template <typename Ts, typename Tc> struct SapArgs {
     const Ts *b;
     const Ts *xr;           // where neighbours' x is read (x itself, or a snapshot)
     Ts *x;
+    // even-odd block solver: A^-1 per site (clover layout), block offsets in parity order,
+    // number of even sites of a block
+    const Tc *cloverinv;
+    const int32_t *eo_sites;
+    int Ve;
 };
 
 // The block residual rho lives in LDS as (re, im) pairs, [12][Vb][T]: lane (off, t)
@@ -216,6 +223,219 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     }
 }
 
+// The even-odd block solver (DD-alpha-AMG's): with a block's sites split by the parity of
+// their block-local coordinate sum (every block extent even, so each hop inside the block
+// joins opposite parities), D_j = A + H is solved through the Schur complement over the
+// even sites, S = A_ee - H_eo A_oo^-1 H_oe:
+//   rhat_e = r_e - H_eo A_oo^-1 r_o,  n_mr MR steps on S e_e = rhat_e,  e_o = A_oo^-1 (r_o - H_oe e_e).
+// Threads take the block's sites in parity order (the even half first), so each phase runs
+// on whole wavefronts of one parity.  LDS holds rho on the even sites; on the odd sites it
+// holds -A_oo^-1 H_oe rho for the step in progress, so that the even sites' hops add
+// -H_eo A_oo^-1 H_oe rho to A_ee rho directly.
+template <typename Ts, typename Tc, int T>
+__device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile, unsigned char *smem)
+{
+    using P2 = typename LdsPair<Tc>::type;
+    const KGeo &g = a.g;
+    P2 *rho = reinterpret_cast<P2 *>(smem);
+    const int str = g.Vb * T;
+    Tc *red_s = reinterpret_cast<Tc *>(rho + 12 * str);  // [waves][T][3]
+
+    const int u = threadIdx.x / T, t = threadIdx.x % T;
+    const bool active = u < g.Vb;
+    const bool ev = active && u < a.Ve, od = active && u >= a.Ve;
+    const int off = active ? a.eo_sites[u] : 0;
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;
+    const int me = off * T + t;
+    int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
+    if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
+
+    // 1. residual on the block
+    Spinor<Tc> r;
+    spinor_zero(r);
+    if (active) {
+        if (a.mode != 0) {
+            const int colour = a.colour, mode = a.mode;
+            const uint32_t *bcs = a.blk_coords;
+            auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
+            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+            Spinor<Tc> bb;
+            load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                r.re[c] = bb.re[c] - r.re[c];
+                r.im[c] = bb.im[c] - r.im[c];
+            }
+        } else {
+            load_spinor<Tc>(g, a.b, grp, blk, off, tt, r);
+        }
+    }
+    // 2. odd sites: e = A_oo^-1 r_o (kept), -e to LDS; even sites: rhat_e = r_e + H_eo (-e)
+    Spinor<Tc> e;
+    spinor_zero(e);
+    if (od) {
+        const int ns = blk * g.Vb + off;
+        clover_site(a.cloverinv, g.V, ns, r, e);
+        Spinor<Tc> m;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            m.re[c] = -e.re[c];
+            m.im[c] = -e.im[c];
+        }
+        lds_store<Tc>(rho, str, me, m);
+    }
+    __syncthreads();
+    if (ev) {
+        const int ns = blk * g.Vb + off;
+        block_hops<0>(g, a.links, rho, T, ns, off, t, lc, r);
+        hop_fence(r);
+        block_hops<1>(g, a.links, rho, T, ns, off, t, lc, r);
+        hop_fence(r);
+        block_hops<2>(g, a.links, rho, T, ns, off, t, lc, r);
+        hop_fence(r);
+        block_hops<3>(g, a.links, rho, T, ns, off, t, lc, r);
+        lds_store<Tc>(rho, str, me, r);
+    }
+
+    // 3. minimal residual on S over the even sites (e of the odd sites holds A_oo^-1 r_o)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int it = 0; it < a.n_mr; ++it) {
+        __syncthreads();
+        if (od) {
+            // odd slots: -A_oo^-1 H_oe rho
+            const int ns = opaque_index(blk * g.Vb + off);
+            Spinor<Tc> h, w;
+            spinor_zero(h);
+            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
+            hop_fence(h);
+            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, h);
+            hop_fence(h);
+            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, h);
+            hop_fence(h);
+            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, h);
+            hop_fence(h);
+            clover_site(a.cloverinv, g.V, ns, h, w);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                w.re[c] = -w.re[c];
+                w.im[c] = -w.im[c];
+            }
+            lds_store<Tc>(rho, str, me, w);
+        }
+        __syncthreads();
+        Spinor<Tc> q;
+        Tc qq = 0, qrr = 0, qri = 0;
+        if (ev) {
+            const int ns = opaque_index(blk * g.Vb + off);
+            {
+                Spinor<Tc> own;
+                lds_load<Tc>(rho, str, me, own);
+                clover_site(a.clover, g.V, ns, own, q);
+            }
+            hop_fence(q);
+            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, q);
+            hop_fence(q);
+            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, q);
+            hop_fence(q);
+            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, q);
+            hop_fence(q);
+            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, q);
+            hop_fence(q);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const P2 o = rho[c * str + me];
+                qq += q.re[c] * q.re[c];
+                qq += q.im[c] * q.im[c];
+                qrr += q.re[c] * o.x;
+                qrr += q.im[c] * o.y;
+                qri += q.re[c] * o.y;
+                qri -= q.im[c] * o.x;
+            }
+        } else {
+            spinor_zero(q);
+        }
+        qq = wave_sum_stride(qq, T);
+        qrr = wave_sum_stride(qrr, T);
+        qri = wave_sum_stride(qri, T);
+        if (lane < T) {
+            red_s[(wave * T + lane) * 3 + 0] = qq;
+            red_s[(wave * T + lane) * 3 + 1] = qrr;
+            red_s[(wave * T + lane) * 3 + 2] = qri;
+        }
+        __syncthreads();
+        Tc sqq = 0, sr = 0, si = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            sqq += red_s[(w * T + t) * 3 + 0];
+            sr += red_s[(w * T + t) * 3 + 1];
+            si += red_s[(w * T + t) * 3 + 2];
+        }
+        const Tc ar = sqq > Tc(0) ? sr / sqq : Tc(0);
+        const Tc ai = sqq > Tc(0) ? si / sqq : Tc(0);
+        if (ev) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const P2 o = rho[c * str + me];
+                e.re[c] += ar * o.x;
+                e.re[c] -= ai * o.y;
+                e.im[c] += ar * o.y;
+                e.im[c] += ai * o.x;
+                Tc nr = o.x, ni = o.y;
+                nr -= ar * q.re[c];
+                nr += ai * q.im[c];
+                ni -= ar * q.im[c];
+                ni -= ai * q.re[c];
+                rho[c * str + me] = {nr, ni};
+            }
+        }
+    }
+
+    // 4. odd sites: e_o = A_oo^-1 r_o + A_oo^-1 H_oe (-e_e)
+    __syncthreads();
+    if (ev) {
+        Spinor<Tc> m;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            m.re[c] = -e.re[c];
+            m.im[c] = -e.im[c];
+        }
+        lds_store<Tc>(rho, str, me, m);
+    }
+    __syncthreads();
+    if (od) {
+        const int ns = blk * g.Vb + off;
+        Spinor<Tc> h, w;
+        spinor_zero(h);
+        block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
+        hop_fence(h);
+        block_hops<1>(g, a.links, rho, T, ns, off, t, lc, h);
+        hop_fence(h);
+        block_hops<2>(g, a.links, rho, T, ns, off, t, lc, h);
+        hop_fence(h);
+        block_hops<3>(g, a.links, rho, T, ns, off, t, lc, h);
+        hop_fence(h);
+        clover_site(a.cloverinv, g.V, ns, h, w);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            e.re[c] += w.re[c];
+            e.im[c] += w.im[c];
+        }
+    }
+
+    // 5. x|_j (+)= e
+    if (active) {
+        if (a.mode == 2) {
+            Spinor<Tc> xo;
+            load_spinor<Tc>(g, a.x, grp, blk, off, tt, xo);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                e.re[c] += xo.re[c];
+                e.im[c] += xo.im[c];
+            }
+        }
+        store_spinor(g, a.x, grp, blk, off, tt, e);
+    }
+}
+
 // Several operators (lattices of uneven size, each with its own right-hand sides) in one
 // launch per half-sweep: workgroup w (after the XCD remap) belongs to the instance whose
 // range [first[k], first[k+1]) holds it.  Descriptors travel by value in the kernel
@@ -239,6 +459,20 @@ __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
     const int li = w - B.first[k];
     const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
     sap_block<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
+}
+
+// the same with the even-odd block solver
+template <typename Ts, typename Tc, int T>
+__global__ void __launch_bounds__(256 * T) k_sap_batched_eo(SapBatch<Ts, Tc> B)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int w = xcd_remap(blockIdx.x, B.first[B.n_inst]);
+    int k = 0;
+    while (k + 1 < B.n_inst && w >= B.first[k + 1]) ++k;
+    const SapArgs<Ts, Tc> &a = B.inst[k];
+    const int li = w - B.first[k];
+    const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
+    sap_block_eo<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
 }
 
 struct CopyBatch {
@@ -271,22 +505,30 @@ template <> const float *op_links<float>(const mrhs_op *op) { return op->links32
 template <typename Tc> const Tc *op_clover(const mrhs_op *op);
 template <> const double *op_clover<double>(const mrhs_op *op) { return op->clover64; }
 template <> const float *op_clover<float>(const mrhs_op *op) { return op->clover32; }
+template <typename Tc> const Tc *op_cloverinv(const mrhs_op *op);
+template <> const double *op_cloverinv<double>(const mrhs_op *op) { return op->cloverinv64; }
+template <> const float *op_cloverinv<float>(const mrhs_op *op) { return op->cloverinv32; }
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
-template <typename Ts, typename Tc, int T>
+template <typename Ts, typename Tc, int T, bool EO>
 int launch_batched(const SapBatch<Ts, Tc> &B, int threads, size_t lds, hipStream_t st)
 {
+    const void *fn = EO ? (const void *)k_sap_batched_eo<Ts, Tc, T> : (const void *)k_sap_batched<Ts, Tc, T>;
     static size_t done = 0;
     if (lds > 65536 && lds > done) {
-        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_sap_batched<Ts, Tc, T>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+        if (int rc = hip_check(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
                                "hipFuncSetAttribute(batched sap LDS)"))
             return rc;
         done = lds;
     }
-    hipLaunchKernelGGL((k_sap_batched<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
-    return hip_check(hipGetLastError(), "k_sap_batched launch");
+    if constexpr (EO) {
+        hipLaunchKernelGGL((k_sap_batched_eo<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
+        return hip_check(hipGetLastError(), "k_sap_batched_eo launch");
+    } else {
+        hipLaunchKernelGGL((k_sap_batched<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
+        return hip_check(hipGetLastError(), "k_sap_batched launch");
+    }
 }
 
 template <typename Ts, typename Tc>
@@ -296,9 +538,12 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
     // one tile for the whole batch: the smallest of the operators' tiles (all divide S)
     int T = 4, maxVb = 0;
     size_t max_lds = ops[0]->max_lds;
+    const bool eo = ops[0]->block_solver == MRHS_BLOCK_EO_MR;
     for (int k = 0; k < n; ++k) {
         T = std::min(T, ops[k]->sap_tile);
         maxVb = std::max(maxVb, ops[k]->k.Vb);
+        if ((ops[k]->block_solver == MRHS_BLOCK_EO_MR) != eo)
+            return set_error(MRHS_EINVAL, "the operators of a batch use different block solvers");
     }
     const int threads = round64(maxVb * T);
     const size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + (size_t)(threads / 64) * T * 3);
@@ -328,6 +573,9 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
         a.n_mr = n_mr;
         a.b = (const Ts *)b[k];
         a.x = (Ts *)x[k];
+        a.cloverinv = op_cloverinv<Tc>(op);
+        a.eo_sites = op->eo_sites;
+        a.Ve = op->k.Vb / 2;
         if (op->odd_blocks) {
             snap[k] = (Ts *)wp;
             wp += align256(native_elems(op, n_rhs[k]) * sizeof(Ts));
@@ -360,10 +608,13 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
             }
             if (B.first[n] == 0) continue;
             int rc;
-            switch (T) {
-            case 1: rc = launch_batched<Ts, Tc, 1>(B, threads, lds, st); break;
-            case 2: rc = launch_batched<Ts, Tc, 2>(B, threads, lds, st); break;
-            case 4: rc = launch_batched<Ts, Tc, 4>(B, threads, lds, st); break;
+            switch (T * 2 + (eo ? 1 : 0)) {
+            case 2: rc = launch_batched<Ts, Tc, 1, false>(B, threads, lds, st); break;
+            case 4: rc = launch_batched<Ts, Tc, 2, false>(B, threads, lds, st); break;
+            case 8: rc = launch_batched<Ts, Tc, 4, false>(B, threads, lds, st); break;
+            case 3: rc = launch_batched<Ts, Tc, 1, true>(B, threads, lds, st); break;
+            case 5: rc = launch_batched<Ts, Tc, 2, true>(B, threads, lds, st); break;
+            case 9: rc = launch_batched<Ts, Tc, 4, true>(B, threads, lds, st); break;
             default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
             }
             if (rc) return rc;

@@ -16,6 +16,7 @@ _LIB_PATH = os.path.join(_HERE, "libmrhs.so")
 MRHS_OK, MRHS_EINVAL, MRHS_EUNSUPPORTED, MRHS_EHIP, MRHS_ERANK, MRHS_ERANGE = 0, -1, -2, -3, -4, -5
 DTYPE_F64, DTYPE_F32, DTYPE_F16 = 0, 1, 2
 PREC_F64, PREC_F32, PREC_F32_F16STORE = 0, 1, 2
+BLOCK_MR, BLOCK_EO_MR = 0, 1
 TORCH_DTYPE = {DTYPE_F64: torch.float64, DTYPE_F32: torch.float32, DTYPE_F16: torch.float16}
 
 
@@ -56,6 +57,7 @@ def lib():
             "block_orthonormalize": (i32, [p, p, i32, p, i32, i32, p, p, sz, p]),
             "coarse_op_build": (i32, [p, p, i32, i32, p, p, sz, p]),
             "mrhs_set_tiles": (i32, [p, i32, i32]),
+            "mrhs_set_block_solver": (i32, [p, i32, p]),
             "sap_smooth_mrhs_batched": (i32, [p, i32, p, p, p, i32, i32, p, sz, p]),
             "mrhs_batched_workspace_bytes": (sz, [p, i32, p]),
             "mrhs_coarse_vector_bytes": (sz, [p, i32, i32]),
@@ -234,6 +236,11 @@ def sap_smooth_mrhs_batched(ops, bs, xs, n_rhs, n_sap, n_mr, ws, stream=None):
 
 def mrhs_set_tiles(op, sap_tile=0, dirac_tile=0):
     _check(lib().mrhs_set_tiles(op, int(sap_tile), int(dirac_tile)))
+
+
+def mrhs_set_block_solver(op, solver, stream=None):
+    """BLOCK_MR (plain MR on D_j) or BLOCK_EO_MR (MR on the block's even-site Schur complement)."""
+    _check(lib().mrhs_set_block_solver(op, int(solver), _stream(stream)))
 
 
 class Operator:
