@@ -175,6 +175,31 @@ def time_call(fn, reps, warmup=2):
     return a.elapsed_time(b) / reps
 
 
+def eo_bench(U, v, plain_ms, plain_res, reps=10):
+    """SAP with the even-odd block solver (MR on each block's even-site Schur complement) on
+    the same workload: time and the largest relative residual ||b - D x|| / ||b|| after the
+    call, for n_MR = 2, 3, 4 (tile: the fastest of 1, 2, 4 at n_MR = 4), beside plain MR."""
+    s = Setup(U, v, mrhs.PREC_F32, 4, gs=False)
+    mrhs.mrhs_set_block_solver(s.op.handle, mrhs.BLOCK_EO_MR)
+    best = None
+    for tile in (1, 2, 4):
+        mrhs.mrhs_set_tiles(s.op.handle, tile, 0)
+        ms = time_call(s.sap, reps)
+        if best is None or ms < best[1]:
+            best = (tile, ms)
+    mrhs.mrhs_set_tiles(s.op.handle, best[0], 0)
+    out = {"tile": best[0], "plain_mr": {"n_mr": N_MR, "ms": round(plain_ms, 4), "residual_max": plain_res}}
+    for n_mr in (2, 3, 4):
+        fn = lambda: mrhs.sap_smooth_mrhs(s.op.handle, s.b, s.x, s.n, N_SAP, n_mr, s.ws)
+        ms = time_call(fn, reps)
+        fn()
+        s.resid()
+        torch.cuda.synchronize()
+        out["eo_n_mr_%d" % n_mr] = {"ms": round(ms, 4), "residual_max": float(s.res.max().item())}
+    s.op.close()
+    return out
+
+
 BATCH = [([8, 8, 8, 8], 401, 8), ([12, 12, 12, 12], 411, 16), ([16, 16, 16, 32], 421, 24), ([24, 24, 24, 48], 431, 32)]
 
 
@@ -334,6 +359,7 @@ def main():
     ap.add_argument("--no-srhs", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
+    ap.add_argument("--no-eo", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -407,6 +433,12 @@ def main():
     coarse_grid = coarse_grid_bench(mr)
     log("coarse grid %s" % coarse_grid)
 
+    eo = None
+    if not args.no_eo:
+        log("even-odd block solver")
+        eo = eo_bench(U, v, per["sap"], float(res.max()))
+        log("eo %s" % eo)
+
     refinement = None
     if not args.no_refine:
         log("refinement phase")
@@ -449,6 +481,7 @@ def main():
         "sap": sap_info,
         "srhs": srhs,
         "coarse_grid": coarse_grid,
+        "even_odd_block_solver": eo,
         "refinement": refinement,
         "batched": batched,
         "cpu_baseline": cpu,

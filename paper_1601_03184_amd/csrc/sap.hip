@@ -243,50 +243,59 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
 
     const int u = threadIdx.x / T, t = threadIdx.x % T;
     const bool active = u < g.Vb;
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;
+    // global-memory phases (residual, x update) in site order, for coalesced vector access
+    const int offn = u, men = offn * T + t;
+    int bcn[4] = {0, 0, 0, 0}, lcn[4] = {0, 0, 0, 0};
+    if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, offn, bcn, lcn);
+    // block-solve phases in parity order
     const bool ev = active && u < a.Ve, od = active && u >= a.Ve;
     const int off = active ? a.eo_sites[u] : 0;
-    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;
     const int me = off * T + t;
     int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
     if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
 
-    // 1. residual on the block
-    Spinor<Tc> r;
-    spinor_zero(r);
+    // 1. residual on the block, to LDS
     if (active) {
+        Spinor<Tc> r;
         if (a.mode != 0) {
             const int colour = a.colour, mode = a.mode;
             const uint32_t *bcs = a.blk_coords;
             auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
-            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, offn, bcn, lcn, r, skip);
             Spinor<Tc> bb;
-            load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+            load_spinor<Tc>(g, a.b, grp, blk, offn, tt, bb);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 r.re[c] = bb.re[c] - r.re[c];
                 r.im[c] = bb.im[c] - r.im[c];
             }
         } else {
-            load_spinor<Tc>(g, a.b, grp, blk, off, tt, r);
+            load_spinor<Tc>(g, a.b, grp, blk, offn, tt, r);
         }
+        lds_store<Tc>(rho, str, men, r);
     }
+    __syncthreads();
     // 2. odd sites: e = A_oo^-1 r_o (kept), -e to LDS; even sites: rhat_e = r_e + H_eo (-e)
     Spinor<Tc> e;
     spinor_zero(e);
     if (od) {
         const int ns = blk * g.Vb + off;
+        Spinor<Tc> r;
+        lds_load<Tc>(rho, str, me, r);
         clover_site(a.cloverinv, g.V, ns, r, e);
-        Spinor<Tc> m;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            m.re[c] = -e.re[c];
-            m.im[c] = -e.im[c];
+            r.re[c] = -e.re[c];
+            r.im[c] = -e.im[c];
         }
-        lds_store<Tc>(rho, str, me, m);
+        lds_store<Tc>(rho, str, me, r);
     }
     __syncthreads();
     if (ev) {
         const int ns = blk * g.Vb + off;
+        Spinor<Tc> r;
+        lds_load<Tc>(rho, str, me, r);
         block_hops<0>(g, a.links, rho, T, ns, off, t, lc, r);
         hop_fence(r);
         block_hops<1>(g, a.links, rho, T, ns, off, t, lc, r);
@@ -421,18 +430,22 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
         }
     }
 
-    // 5. x|_j (+)= e
+    // 5. e to LDS, then x|_j (+)= e in site order
+    __syncthreads();
+    if (active) lds_store<Tc>(rho, str, me, e);
+    __syncthreads();
     if (active) {
+        lds_load<Tc>(rho, str, men, e);
         if (a.mode == 2) {
             Spinor<Tc> xo;
-            load_spinor<Tc>(g, a.x, grp, blk, off, tt, xo);
+            load_spinor<Tc>(g, a.x, grp, blk, offn, tt, xo);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 e.re[c] += xo.re[c];
                 e.im[c] += xo.im[c];
             }
         }
-        store_spinor(g, a.x, grp, blk, off, tt, e);
+        store_spinor(g, a.x, grp, blk, offn, tt, e);
     }
 }
 
