@@ -233,6 +233,76 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
 // holds -A_oo^-1 H_oe rho for the step in progress, so that the even sites' hops add
 // -H_eo A_oo^-1 H_oe rho to A_ee rho directly.
 template <typename Ts, typename Tc, int T>
+__device__ inline void eo_hops(const SapArgs<Ts, Tc> &a, const typename LdsPair<Tc>::type *rho, int ns, int off, int t,
+                               const int (&lc)[4], Spinor<Tc> &h)
+{
+    const KGeo &g = a.g;
+    block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
+    hop_fence(h);
+    block_hops<1>(g, a.links, rho, T, ns, off, t, lc, h);
+    hop_fence(h);
+    block_hops<2>(g, a.links, rho, T, ns, off, t, lc, h);
+    hop_fence(h);
+    block_hops<3>(g, a.links, rho, T, ns, off, t, lc, h);
+    hop_fence(h);
+}
+
+template <typename Ts, typename Tc, int T>
+__device__ inline void eo_residual(const SapArgs<Ts, Tc> &a, typename LdsPair<Tc>::type *rho, int blk, int off, int grp,
+                                   int tt, int t)
+{
+    const KGeo &g = a.g;
+    int bc[4], lc[4];
+    decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
+    Spinor<Tc> r;
+    if (a.mode != 0) {
+        const int colour = a.colour, mode = a.mode;
+        const uint32_t *bcs = a.blk_coords;
+        auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
+        dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+        Spinor<Tc> bb;
+        load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            r.re[c] = bb.re[c] - r.re[c];
+            r.im[c] = bb.im[c] - r.im[c];
+        }
+    } else {
+        load_spinor<Tc>(g, a.b, grp, blk, off, tt, r);
+    }
+    lds_store<Tc>(rho, g.Vb * T, off * T + t, r);
+}
+
+template <typename Ts, typename Tc, int T>
+__device__ inline void eo_update_x(const SapArgs<Ts, Tc> &a, const typename LdsPair<Tc>::type *rho, int blk, int off,
+                                   int grp, int tt, int t)
+{
+    const KGeo &g = a.g;
+    Spinor<Tc> e;
+    lds_load<Tc>(rho, g.Vb * T, off * T + t, e);
+    if (a.mode == 2) {
+        Spinor<Tc> xo;
+        load_spinor<Tc>(g, a.x, grp, blk, off, tt, xo);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            e.re[c] += xo.re[c];
+            e.im[c] += xo.im[c];
+        }
+    }
+    store_spinor(g, a.x, grp, blk, off, tt, e);
+}
+
+// The even-odd block solver (DD-alpha-AMG's): with a block's sites split by the parity of
+// their block-local coordinate sum (every block extent even, so each hop inside the block
+// joins opposite parities), D_j = A + H is solved through the Schur complement over the
+// even sites, S = A_ee - H_eo A_oo^-1 H_oe:
+//   rhat_e = r_e - H_eo A_oo^-1 r_o,  n_mr MR steps on S e_e = rhat_e,  e_o = A_oo^-1 (r_o - H_oe e_e).
+// Each thread owns one even and one odd site of the block (the u-th of each, parity order),
+// so the workgroup has Vb / 2 x T threads and all of them work in both phases of a step: the
+// odd sites' hops and A^-1, then the even sites' clover and hops.  LDS holds rho on the even
+// sites and -A_oo^-1 H_oe rho on the odd sites; the residual and the x update run in site
+// order (sites u and u + Vb / 2) for coalesced vector access and go through LDS.
+template <typename Ts, typename Tc, int T>
 __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile, unsigned char *smem)
 {
     using P2 = typename LdsPair<Tc>::type;
@@ -241,115 +311,78 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
     const int str = g.Vb * T;
     Tc *red_s = reinterpret_cast<Tc *>(rho + 12 * str);  // [waves][T][3]
 
-    const int u = threadIdx.x / T, t = threadIdx.x % T;
-    const bool active = u < g.Vb;
+    const int u = threadIdx.x / T, t = threadIdx.x % T, Ve = a.Ve;
+    const bool active = u < Ve;
     const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;
-    // global-memory phases (residual, x update) in site order, for coalesced vector access
-    const int offn = u, men = offn * T + t;
-    int bcn[4] = {0, 0, 0, 0}, lcn[4] = {0, 0, 0, 0};
-    if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, offn, bcn, lcn);
-    // block-solve phases in parity order
-    const bool ev = active && u < a.Ve, od = active && u >= a.Ve;
-    const int off = active ? a.eo_sites[u] : 0;
-    const int me = off * T + t;
-    int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
-    if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
-
-    // 1. residual on the block, to LDS
+    const int se = active ? a.eo_sites[u] : 0, so = active ? a.eo_sites[Ve + u] : 0;
+    const int me = se * T + t, mo = so * T + t;
+    int bc[4] = {0, 0, 0, 0}, lce[4] = {0, 0, 0, 0}, lco[4] = {0, 0, 0, 0};
     if (active) {
-        Spinor<Tc> r;
-        if (a.mode != 0) {
-            const int colour = a.colour, mode = a.mode;
-            const uint32_t *bcs = a.blk_coords;
-            auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
-            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, offn, bcn, lcn, r, skip);
-            Spinor<Tc> bb;
-            load_spinor<Tc>(g, a.b, grp, blk, offn, tt, bb);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                r.re[c] = bb.re[c] - r.re[c];
-                r.im[c] = bb.im[c] - r.im[c];
-            }
-        } else {
-            load_spinor<Tc>(g, a.b, grp, blk, offn, tt, r);
-        }
-        lds_store<Tc>(rho, str, men, r);
+        decode_site(g, a.blk_coords, a.loc_coords, blk, se, bc, lce);
+        decode_site(g, a.blk_coords, a.loc_coords, blk, so, bc, lco);
+    }
+
+    // 1. residual on the block (sites u and u + Ve in site order), to LDS
+    if (active) {
+        eo_residual<Ts, Tc, T>(a, rho, blk, u, grp, tt, t);
+        eo_residual<Ts, Tc, T>(a, rho, blk, u + Ve, grp, tt, t);
     }
     __syncthreads();
-    // 2. odd sites: e = A_oo^-1 r_o (kept), -e to LDS; even sites: rhat_e = r_e + H_eo (-e)
-    Spinor<Tc> e;
-    spinor_zero(e);
-    if (od) {
-        const int ns = blk * g.Vb + off;
+    // 2. odd: eo = A_oo^-1 r_o (kept), -eo to LDS; even: rhat_e = r_e + H_eo (-eo)
+    Spinor<Tc> ee, eo;
+    spinor_zero(ee);
+    spinor_zero(eo);
+    if (active) {
+        const int ns = blk * g.Vb + so;
         Spinor<Tc> r;
-        lds_load<Tc>(rho, str, me, r);
-        clover_site(a.cloverinv, g.V, ns, r, e);
+        lds_load<Tc>(rho, str, mo, r);
+        clover_site(a.cloverinv, g.V, ns, r, eo);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            r.re[c] = -e.re[c];
-            r.im[c] = -e.im[c];
+            r.re[c] = -eo.re[c];
+            r.im[c] = -eo.im[c];
         }
-        lds_store<Tc>(rho, str, me, r);
+        lds_store<Tc>(rho, str, mo, r);
     }
     __syncthreads();
-    if (ev) {
-        const int ns = blk * g.Vb + off;
+    if (active) {
+        const int ns = blk * g.Vb + se;
         Spinor<Tc> r;
         lds_load<Tc>(rho, str, me, r);
-        block_hops<0>(g, a.links, rho, T, ns, off, t, lc, r);
-        hop_fence(r);
-        block_hops<1>(g, a.links, rho, T, ns, off, t, lc, r);
-        hop_fence(r);
-        block_hops<2>(g, a.links, rho, T, ns, off, t, lc, r);
-        hop_fence(r);
-        block_hops<3>(g, a.links, rho, T, ns, off, t, lc, r);
+        eo_hops<Ts, Tc, T>(a, rho, ns, se, t, lce, r);
         lds_store<Tc>(rho, str, me, r);
     }
 
-    // 3. minimal residual on S over the even sites (e of the odd sites holds A_oo^-1 r_o)
+    // 3. minimal residual on S over the even sites
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     for (int it = 0; it < a.n_mr; ++it) {
         __syncthreads();
-        if (od) {
+        if (active) {
             // odd slots: -A_oo^-1 H_oe rho
-            const int ns = opaque_index(blk * g.Vb + off);
+            const int ns = opaque_index(blk * g.Vb + so);
             Spinor<Tc> h, w;
             spinor_zero(h);
-            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
-            hop_fence(h);
-            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, h);
-            hop_fence(h);
-            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, h);
-            hop_fence(h);
-            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, h);
-            hop_fence(h);
+            eo_hops<Ts, Tc, T>(a, rho, ns, so, t, lco, h);
             clover_site(a.cloverinv, g.V, ns, h, w);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 w.re[c] = -w.re[c];
                 w.im[c] = -w.im[c];
             }
-            lds_store<Tc>(rho, str, me, w);
+            lds_store<Tc>(rho, str, mo, w);
         }
         __syncthreads();
         Spinor<Tc> q;
         Tc qq = 0, qrr = 0, qri = 0;
-        if (ev) {
-            const int ns = opaque_index(blk * g.Vb + off);
+        if (active) {
+            const int ns = opaque_index(blk * g.Vb + se);
             {
                 Spinor<Tc> own;
                 lds_load<Tc>(rho, str, me, own);
                 clover_site(a.clover, g.V, ns, own, q);
             }
             hop_fence(q);
-            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, q);
-            hop_fence(q);
-            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, q);
-            hop_fence(q);
-            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, q);
-            hop_fence(q);
-            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, q);
-            hop_fence(q);
+            eo_hops<Ts, Tc, T>(a, rho, ns, se, t, lce, q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const P2 o = rho[c * str + me];
@@ -380,14 +413,14 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
         }
         const Tc ar = sqq > Tc(0) ? sr / sqq : Tc(0);
         const Tc ai = sqq > Tc(0) ? si / sqq : Tc(0);
-        if (ev) {
+        if (active) {
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const P2 o = rho[c * str + me];
-                e.re[c] += ar * o.x;
-                e.re[c] -= ai * o.y;
-                e.im[c] += ar * o.y;
-                e.im[c] += ai * o.x;
+                ee.re[c] += ar * o.x;
+                ee.re[c] -= ai * o.y;
+                ee.im[c] += ar * o.y;
+                ee.im[c] += ai * o.x;
                 Tc nr = o.x, ni = o.y;
                 nr -= ar * q.re[c];
                 nr += ai * q.im[c];
@@ -398,54 +431,41 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
         }
     }
 
-    // 4. odd sites: e_o = A_oo^-1 r_o + A_oo^-1 H_oe (-e_e)
+    // 4. odd: e_o = A_oo^-1 r_o + A_oo^-1 H_oe (-e_e)
     __syncthreads();
-    if (ev) {
+    if (active) {
         Spinor<Tc> m;
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            m.re[c] = -e.re[c];
-            m.im[c] = -e.im[c];
+            m.re[c] = -ee.re[c];
+            m.im[c] = -ee.im[c];
         }
         lds_store<Tc>(rho, str, me, m);
     }
     __syncthreads();
-    if (od) {
-        const int ns = blk * g.Vb + off;
+    if (active) {
+        const int ns = blk * g.Vb + so;
         Spinor<Tc> h, w;
         spinor_zero(h);
-        block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
-        hop_fence(h);
-        block_hops<1>(g, a.links, rho, T, ns, off, t, lc, h);
-        hop_fence(h);
-        block_hops<2>(g, a.links, rho, T, ns, off, t, lc, h);
-        hop_fence(h);
-        block_hops<3>(g, a.links, rho, T, ns, off, t, lc, h);
-        hop_fence(h);
+        eo_hops<Ts, Tc, T>(a, rho, ns, so, t, lco, h);
         clover_site(a.cloverinv, g.V, ns, h, w);
 #pragma unroll
         for (int c = 0; c < 12; ++c) {
-            e.re[c] += w.re[c];
-            e.im[c] += w.im[c];
+            eo.re[c] += w.re[c];
+            eo.im[c] += w.im[c];
         }
     }
 
     // 5. e to LDS, then x|_j (+)= e in site order
     __syncthreads();
-    if (active) lds_store<Tc>(rho, str, me, e);
+    if (active) {
+        lds_store<Tc>(rho, str, me, ee);
+        lds_store<Tc>(rho, str, mo, eo);
+    }
     __syncthreads();
     if (active) {
-        lds_load<Tc>(rho, str, men, e);
-        if (a.mode == 2) {
-            Spinor<Tc> xo;
-            load_spinor<Tc>(g, a.x, grp, blk, offn, tt, xo);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                e.re[c] += xo.re[c];
-                e.im[c] += xo.im[c];
-            }
-        }
-        store_spinor(g, a.x, grp, blk, offn, tt, e);
+        eo_update_x<Ts, Tc, T>(a, rho, blk, u, grp, tt, t);
+        eo_update_x<Ts, Tc, T>(a, rho, blk, u + Ve, grp, tt, t);
     }
 }
 
@@ -476,7 +496,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
 
 // the same with the even-odd block solver
 template <typename Ts, typename Tc, int T>
-__global__ void __launch_bounds__(256 * T) k_sap_batched_eo(SapBatch<Ts, Tc> B)
+__global__ void __launch_bounds__(128 * T) k_sap_batched_eo(SapBatch<Ts, Tc> B)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = xcd_remap(blockIdx.x, B.first[B.n_inst]);
@@ -559,6 +579,7 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
             return set_error(MRHS_EINVAL, "the operators of a batch use different block solvers");
     }
     const int threads = round64(maxVb * T);
+    const int eo_threads = round64(maxVb / 2 * T);  // even-odd: one even and one odd site per thread
     const size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + (size_t)(threads / 64) * T * 3);
     if (maxVb * T > 1024 || lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "batched SAP tile does not fit");
     if (n_sap == 0) {
@@ -621,13 +642,14 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
             }
             if (B.first[n] == 0) continue;
             int rc;
+            const int thr = eo ? eo_threads : threads;
             switch (T * 2 + (eo ? 1 : 0)) {
-            case 2: rc = launch_batched<Ts, Tc, 1, false>(B, threads, lds, st); break;
-            case 4: rc = launch_batched<Ts, Tc, 2, false>(B, threads, lds, st); break;
-            case 8: rc = launch_batched<Ts, Tc, 4, false>(B, threads, lds, st); break;
-            case 3: rc = launch_batched<Ts, Tc, 1, true>(B, threads, lds, st); break;
-            case 5: rc = launch_batched<Ts, Tc, 2, true>(B, threads, lds, st); break;
-            case 9: rc = launch_batched<Ts, Tc, 4, true>(B, threads, lds, st); break;
+            case 2: rc = launch_batched<Ts, Tc, 1, false>(B, thr, lds, st); break;
+            case 4: rc = launch_batched<Ts, Tc, 2, false>(B, thr, lds, st); break;
+            case 8: rc = launch_batched<Ts, Tc, 4, false>(B, thr, lds, st); break;
+            case 3: rc = launch_batched<Ts, Tc, 1, true>(B, thr, lds, st); break;
+            case 5: rc = launch_batched<Ts, Tc, 2, true>(B, thr, lds, st); break;
+            case 9: rc = launch_batched<Ts, Tc, 4, true>(B, thr, lds, st); break;
             default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
             }
             if (rc) return rc;
