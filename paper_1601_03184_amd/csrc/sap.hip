@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
 
 // the same with the even-odd block solver
 template <typename Ts, typename Tc, int T>
-__global__ void __launch_bounds__(128 * T) k_sap_batched_eo(SapBatch<Ts, Tc> B)
+__global__ void __launch_bounds__(128 * T, T == 2 ? 3 : 1) k_sap_batched_eo(SapBatch<Ts, Tc> B)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = xcd_remap(blockIdx.x, B.first[B.n_inst]);
