@@ -260,9 +260,20 @@ def coarse_grid_bench(mr, reps=20):
     coarse = op.n_agg * 2 * n * 2 * 4 * n       # n FP32 coarse vectors
     dcb = op.n_agg * 9 * (2 * n) ** 2 * 8
     out = {}
+    # FP16 storage of Q (reduced-precision test vectors for R, P and D_c; FP32 arithmetic)
+    D16 = mrhs.DTYPE_F16
+    q16 = op.empty(n, D16)
+    mrhs.block_orthonormalize(op.handle, mr.x, op.dtype, q16, D16, n, None, None)
+    t_r16 = time_call(lambda: mrhs.restrict_mrhs(op.handle, q16, D16, n, mr.x, op.dtype, yc, n), reps)
+    t_p16 = time_call(lambda: mrhs.prolong_mrhs(op.handle, q16, D16, n, yc, y, op.dtype, n), reps)
+    dc16 = torch.empty_like(mr.Dc)
+    t_dc32 = time_call(lambda: mrhs.coarse_op_build(op.handle, mr.Q, mrhs.DTYPE_F32, n, dc16, None), 5)
+    t_dc16 = time_call(lambda: mrhs.coarse_op_build(op.handle, q16, D16, n, dc16, None), 5)
     for name, ms, b in (("restrict", t_r, 2 * fine + coarse), ("prolong", t_p, 2 * fine + coarse),
-                        ("coarse_apply", t_a, dcb + 10 * coarse)):
+                        ("coarse_apply", t_a, dcb + 10 * coarse),
+                        ("restrict_q16", t_r16, 1.5 * fine + coarse), ("prolong_q16", t_p16, 1.5 * fine + coarse)):
         out[name] = {"ms": round(ms, 4), "alg_GBs": round(b / ms / 1e6, 1), "frac_hbm": round(b / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    out["coarse_op_build_ms"] = {"q_fp32": round(t_dc32, 4), "q_fp16": round(t_dc16, 4)}
     return out
 
 

@@ -137,14 +137,16 @@ int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t
  * of V^h_i (6 * aggregate volume rows: local site, spin in half, colour): V^h_i = Q^h_i T
  * with T upper triangular, real positive diagonal (the setup of R = Q^dag, P = Q; Sec. 2,
  * Alg. 3).  FP64 arithmetic.  V: native vectors of v_dtype; Q: native vectors of q_dtype
- * (may alias V exactly when the types agree).  status (DEVICE int32, nullable) receives 0
+ * (may alias V exactly when the types agree); q_dtype F16 stores Q in binary16, each entry
+ * rounded once from FP64 (the entries of an orthonormal column are at most 1 in modulus).  status (DEVICE int32, nullable) receives 0
  * or 1 + (2*aggregate + h) of the first aggregate half whose Cholesky pivot falls to
  * <= 1e-14 ||v_k||^2 (T_kk <= 1e-7 ||v_k||, the resolution limit of CholQR in FP64);
  * such a half's Q is not meaningful.  Needs n_tv <= 32 and n_tv <= 6 * aggregate volume. */
 int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void *Q, int32_t q_dtype, int32_t n_tv,
                          int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
-/* D_c = R D P from Q (the output of block_orthonormalize, q_dtype F32 or F64), stored per
+/* D_c = R D P from Q (the output of block_orthonormalize, q_dtype F64, F32 or F16; the
+ * arithmetic is that of the op's fields, FP32 or FP64, whatever Q's storage), stored per
  * coarse site i (lexicographic over L/agg) as 9 blocks [self,+x,+y,+z,+t,-x,-y,-z,-t],
  * each 2 n_tv x 2 n_tv complex64 row-major, row = h*n_tv + k.  The self block holds the
  * site term and the hops that stay inside the aggregate without crossing its faces; the
@@ -159,7 +161,8 @@ int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n
  * ((i * 2*n_tv + c) * 2 + p) * ldc + k, ldc = n_rhs rounded up to a multiple of 4; the
  * kernels write the padding entries k >= n_rhs as zero.  Arithmetic is FP32 (matrix cores,
  * FP32 accumulation).  1 <= n_tv, n_rhs <= 32.  Q: the output of block_orthonormalize
- * (q_dtype F32 or F64). */
+ * (q_dtype F64, F32 or F16; FP16 storage halves the bytes of Q that restriction, prolongation
+ * and the D_c build read, the arithmetic stays FP32). */
 size_t mrhs_coarse_vector_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs);
 
 /* y_c = R y, R = Q^dag per aggregate and spin half: (y_c)^h_i[j] = sum_n conj(Q^h_i[n, j]) y^h_i[n]

@@ -355,7 +355,6 @@ int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void
     if (int rc = check_dtype(v_dtype)) return rc;
     if (int rc = check_dtype(q_dtype)) return rc;
     if (!V || !Q) return set_error(MRHS_EINVAL, "null vector");
-    if (q_dtype == MRHS_DTYPE_F16) return set_error(MRHS_EUNSUPPORTED, "FP16 output of Gram-Schmidt");
     if (n_tv > 6 * op->Va) return set_error(MRHS_EINVAL, "more test vectors than rows of an aggregate half");
     const size_t ne = native_elems(op, n_tv);
     const bool same = V == Q && v_dtype == q_dtype;  // in place
@@ -372,8 +371,7 @@ int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n
     if (int rc = check_op(op)) return rc;
     if (int rc = check_nrhs(n_tv)) return rc;
     if (!Q || !Dc) return set_error(MRHS_EINVAL, "null argument");
-    if (q_dtype != MRHS_DTYPE_F32 && q_dtype != MRHS_DTYPE_F64)
-        return set_error(MRHS_EUNSUPPORTED, "coarse operator needs FP32 or FP64 test vectors");
+    if (int rc = check_dtype(q_dtype)) return rc;
     (void)ws;
     (void)ws_bytes;
     return launch_coarse(op, Q, q_dtype, n_tv, Dc, (hipStream_t)stream);
@@ -394,8 +392,7 @@ int check_transfer(const mrhs_op *op, int n_tv, int n_rhs, int q_dtype)
     if (int rc = check_nrhs(n_rhs)) return rc;
     if (n_tv > 32 || n_rhs > 32) return set_error(MRHS_EUNSUPPORTED, "at most 32 test vectors and 32 right-hand sides");
     if (n_tv > 6 * op->Va) return set_error(MRHS_EINVAL, "more test vectors than rows of an aggregate half");
-    if (q_dtype != MRHS_DTYPE_F32 && q_dtype != MRHS_DTYPE_F64)
-        return set_error(MRHS_EUNSUPPORTED, "test vectors must be FP32 or FP64");
+    if (int rc = check_dtype(q_dtype)) return rc;
     if (transfer_lds_bytes(op) > op->max_lds) return set_error(MRHS_EUNSUPPORTED, "aggregate too large for the LDS");
     return MRHS_OK;
 }

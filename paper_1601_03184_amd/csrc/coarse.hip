@@ -60,8 +60,8 @@ __device__ inline void load_pcol(const KGeo &g, const Tq *Q, int kp, int ns, Spi
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         if (c / 6 == HP) {
-            s.re[c] = (Tc)Q[base + (2 * c) * cs];
-            s.im[c] = (Tc)Q[base + (2 * c + 1) * cs];
+            s.re[c] = load_as<Tc>(Q + base + (2 * c) * cs);
+            s.im[c] = load_as<Tc>(Q + base + (2 * c + 1) * cs);
         } else {
             s.re[c] = s.im[c] = Tc(0);
         }
@@ -336,9 +336,13 @@ int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc,
     if (op->links32) {
         if (qdt == MRHS_DTYPE_F32)
             return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, st);
+        if (qdt == MRHS_DTYPE_F16)
+            return coarse_dispatch<float, __half>(op, op->links32, op->clover32, (const __half *)Q, n_tv, Dc, st);
         return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, st);
     }
     if (qdt == MRHS_DTYPE_F32)
         return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, st);
+    if (qdt == MRHS_DTYPE_F16)
+        return coarse_dispatch<double, __half>(op, op->links64, op->clover64, (const __half *)Q, n_tv, Dc, st);
     return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, st);
 }

@@ -436,8 +436,8 @@ template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NT
                     const int k = tj * 16 + (lane & 15);
                     if (k >= N) continue;
                     const size_t idx = ro + coff[k];
-                    Q[idx] = (Tq)dr[tj][r];
-                    Q[idx + cstr] = (Tq)di[tj][r];
+                    Q[idx] = store_as<Tq>(dr[tj][r]);
+                    Q[idx + cstr] = store_as<Tq>(di[tj][r]);
                 }
             }
             cur = nxt;
@@ -482,8 +482,9 @@ template <typename Tv, typename Tq> int launch_nt(const GsArgs &a, int n_agg, si
 
 template <typename Tv> int launch_v(const GsArgs &a, int qdt, int n_agg, size_t max_lds, hipStream_t st)
 {
-    return qdt == MRHS_DTYPE_F64 ? launch_nt<Tv, double>(a, n_agg, max_lds, st)
-                                 : launch_nt<Tv, float>(a, n_agg, max_lds, st);
+    if (qdt == MRHS_DTYPE_F64) return launch_nt<Tv, double>(a, n_agg, max_lds, st);
+    if (qdt == MRHS_DTYPE_F32) return launch_nt<Tv, float>(a, n_agg, max_lds, st);
+    return launch_nt<Tv, __half>(a, n_agg, max_lds, st);  // FP16 storage of Q (rounded once from FP64)
 }
 
 }  // namespace

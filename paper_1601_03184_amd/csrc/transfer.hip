@@ -397,7 +397,9 @@ int launch_restrict(const mrhs_op *op, const void *Q, int qdt, int n_tv, const v
     a.Q = Q;
     a.y = y;
     a.yco = yc;
-    return qdt == MRHS_DTYPE_F64 ? restrict_y<double>(a, ydt, st) : restrict_y<float>(a, ydt, st);
+    if (qdt == MRHS_DTYPE_F64) return restrict_y<double>(a, ydt, st);
+    if (qdt == MRHS_DTYPE_F32) return restrict_y<float>(a, ydt, st);
+    return restrict_y<__half>(a, ydt, st);
 }
 
 int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const float *yc, void *y, int ydt, int n,
@@ -407,7 +409,9 @@ int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const fl
     a.Q = Q;
     a.yc = yc;
     a.yo = y;
-    return qdt == MRHS_DTYPE_F64 ? prolong_y<double>(a, ydt, st) : prolong_y<float>(a, ydt, st);
+    if (qdt == MRHS_DTYPE_F64) return prolong_y<double>(a, ydt, st);
+    if (qdt == MRHS_DTYPE_F32) return prolong_y<float>(a, ydt, st);
+    return prolong_y<__half>(a, ydt, st);
 }
 
 int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,

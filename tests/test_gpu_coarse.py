@@ -36,6 +36,8 @@ GS_CASES = [
     ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F16, 4, 24, D16, D64, False, False),
     ([8, 4, 8, 4], [4, 4, 4, 4], [2, 4, 4, 2], F32, 8, 13, D32, D64, False, False),  # aggregates != blocks
     ([4, 4, 4, 8], [2, 2, 2, 2], [4, 4, 4, 4], F64, 2, 32, D64, D64, False, False),  # aggregate = 16 blocks
+    ([8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, D32, D16, False, True),   # FP16 storage of Q
+    ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F16, 4, 24, D16, D16, True, False),   # FP16 in place
 ]
 
 
@@ -54,7 +56,8 @@ def test_gs_parity(L, block, agg, prec, S, n, vdt, qdt, in_place, smooth):
     assert status == 0
     got = op.unpack(Q, n, qdt).cpu().numpy()
     ref = oracle.block_gs(L, agg, vin)
-    tol = 1e-12 if qdt == D64 else 1e-6
+    # FP16 storage: one rounding of each entry (relative 2^-12 at most)
+    tol = {D64: 1e-12, D32: 1e-6, D16: 1e-3}[qdt]
     assert rel(got, ref) < tol, rel(got, ref)
     op.close()
 
@@ -81,6 +84,8 @@ COARSE_CASES = [
     ([8, 4, 8, 4], [4, 4, 4, 4], [2, 4, 4, 2], F32, 8, 13, D32),
     ([4, 4, 2, 4], [2, 2, 2, 2], [2, 4, 2, 2], F32, 4, 4, D32),   # coarse extents 2 and 1
     ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 32, D32),
+    ([8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, D16),   # FP16 storage of Q
+    ([4, 4, 4, 4], [2, 2, 2, 2], [2, 2, 2, 2], F64, 4, 8, D16),
 ]
 
 

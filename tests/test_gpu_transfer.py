@@ -47,6 +47,8 @@ CASES = [
     ([8, 4, 8, 4], [4, 4, 4, 4], [2, 4, 4, 2], F32, 8, 13, 7, D32),     # aggregates != blocks, S = 8
     ([4, 4, 2, 4], [2, 2, 2, 2], [2, 4, 2, 2], F64, 4, 4, 3, D64),      # coarse extents 2 and 1
     ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F16, 4, 32, 32, D32),    # FP16 fine vectors
+    ([8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, 13, D16),    # FP16 storage of Q
+    ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F16, 4, 32, 32, D16),    # FP16 vectors and Q
 ]
 
 
@@ -93,7 +95,7 @@ def test_restrict_prolong_parity(L, block, agg, prec, S, n_tv, n, qdt):
     op.close()
 
 
-@pytest.mark.parametrize("L,block,agg,prec,S,n_tv,n,qdt", CASES[:4])
+@pytest.mark.parametrize("L,block,agg,prec,S,n_tv,n,qdt", CASES[:4] + CASES[5:6])
 def test_coarse_apply_parity(L, block, agg, prec, S, n_tv, n, qdt):
     need_gpu()
     announce("coarse apply L=%s agg=%s n_tv=%d n=%d" % (L, agg, n_tv, n))
@@ -187,29 +189,29 @@ def test_coarse_gmres_parity(L, block, agg, prec, S, n_tv, n, m, tol):
     op.close()
 
 
-@pytest.mark.parametrize("prec", [F32, F64])
-def test_setup_refine_parity(prec):
+@pytest.mark.parametrize("prec,qdt", [(F32, D32), (F64, D32), (F32, D16)])
+def test_setup_refine_parity(prec, qdt):
     """One refinement pass over all test vectors (Alg. 2, N_b = n_tv) against the oracle's
     composition restrict -> GMRES -> prolong -> SAP from the guess, on the same inputs."""
     need_gpu()
     L, block, n_tv, m = [8, 8, 4, 8], [4, 4, 4, 4], 20, 4
     case = Case(L, 0.3, 341, -0.2)
-    announce("setup refine prec=%d" % prec)
+    announce("setup refine prec=%d qdt=%d" % (prec, qdt))
     op = case.op(block, prec=prec, short_len=4)
     vdt = op.dtype
     b0 = op.pack(torch.from_numpy(inputs.test_vectors(L, n_tv, 342)))
     V = op.empty(n_tv)
     mrhs.sap_smooth_mrhs(op.handle, b0, V, n_tv, 2, 3, op.workspace(n_tv))  # initial phase
-    Q = op.empty(n_tv, D32)
-    mrhs.block_orthonormalize(op.handle, V, vdt, Q, D32, n_tv, None, None)
+    Q = op.empty(n_tv, qdt)
+    mrhs.block_orthonormalize(op.handle, V, vdt, Q, qdt, n_tv, None, None)
     nc = 2 * n_tv
     Dc = torch.zeros(op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
-    mrhs.coarse_op_build(op.handle, Q, D32, n_tv, Dc, None)
+    mrhs.coarse_op_build(op.handle, Q, qdt, n_tv, Dc, None)
     vin = op.unpack(V, n_tv).cpu().numpy()
-    qin = op.unpack(Q, n_tv, D32).cpu().numpy()
+    qin = op.unpack(Q, n_tv, qdt).cpu().numpy()
     Dh = Dc.cpu().double().numpy().view(np.complex128).reshape(op.n_agg, 9, nc, nc)
     ws = torch.empty(mrhs.mrhs_refine_workspace_bytes(op.handle, n_tv, m), dtype=torch.uint8, device="cuda")
-    mrhs.setup_refine_mrhs(op.handle, V, n_tv, Q, D32, Dc, 3, 4, m, 0.0, ws)
+    mrhs.setup_refine_mrhs(op.handle, V, n_tv, Q, qdt, Dc, 3, 4, m, 0.0, ws)
     got = op.unpack(V, n_tv).cpu().numpy()
     vc = oracle.restrict(L, block, qin, vin)
     uc, _, _ = oracle.coarse_gmres(L, block, Dh, vc, m)
