@@ -12,6 +12,9 @@ aggregates of Q, and all 9 blocks of D_c at a sampled coarse site.  The oracle's
 that site is computed on a 12^4 window of 3^4 aggregates centred on it: every link,
 clover term and Q entry the centre aggregate's blocks involve lies inside the window.
 
+32^3 x 64 again with the even-odd block solver: two sampled right-hand sides of SAP against
+the oracle's even-odd SAP.
+
 Inputs come from the device generators (seeded; the host generators would take minutes
 at these sizes); the test vectors are packed four at a time.
 """
@@ -187,4 +190,31 @@ def test_c5_full_setup_step():
     for d in range(9):
         err = float(np.linalg.norm(got[d] - ref[d]) / np.linalg.norm(ref[d]))
         assert err < 1e-5, (d, err)
+    op.close()
+
+
+@pytest.mark.timeout(900)
+def test_c3_even_odd_sap_sampled():
+    """32^3 x 64, 24 test vectors, SAP 3 x 4 with the even-odd block solver in FP32: two
+    sampled right-hand sides against the oracle's even-odd SAP"""
+    need_gpu()
+    L, n, seed_u, seed_v, m0 = [32, 32, 32, 64], 24, 301, 302, -0.33
+    announce("full size 32^3x64 n=24: even-odd SAP")
+    U = inputs.gauge_field_device(L, 0.25, seed_u, "cuda")
+    op = mrhs.Operator(L, BLOCK, BLOCK, U, m0, 1.0, prec=F32, short_len=S)
+    mrhs.mrhs_set_block_solver(op.handle, mrhs.BLOCK_EO_MR)
+    b = op.empty(n)
+    pack_all(op, b, D32, L, n, seed_v)
+    x = op.empty(n)
+    mrhs.sap_smooth_mrhs(op.handle, b, x, n, 3, 4, op.workspace(n))
+    torch.cuda.synchronize()
+    Uh = U.cpu().numpy()
+    del U
+    A = oracle.clover(L, Uh, 1.0, m0)
+    Ainv = oracle.clover_inverse(A)
+    for k in (0, n - 1):
+        announce("full size 32^3x64: oracle even-odd SAP rhs %d" % k)
+        bk = inputs.test_vectors_device(L, 1, seed_v, "cuda", first=k).cpu().numpy()
+        ref = oracle.sap(L, BLOCK, Uh, A, bk, 3, 4, eo=True, Ainv=Ainv)
+        assert per_rhs_rel(unpack_rhs(op, x, D32, n, k)[None], ref) < 1e-5
     op.close()
