@@ -57,6 +57,7 @@ def lib():
             "oracle_coarse_gmres": (None, [p, p, p, i, p, p, i, i, ctypes.c_double, p, p]),
             "oracle_coarse_op": (None, [p, p, p, p, p, i, p, p, l]),
             "oracle_eo_block": (i, [p, p, p, p, p, l, p, i, p, p]),
+            "oracle_coarse_gmres_eo": (i, [p, p, p, p, i, p, p, i, i, ctypes.c_double, p, p]),
             "oracle_sap_from_eo": (i, [p, p, p, p, p, p, p, i, i, i]),
         }
         for name, (res, args) in sig.items():
@@ -284,3 +285,31 @@ def coarse_op(L, a, U, A, Q, agg_list=None):
     lib().oracle_coarse_op(_ptr(L), _ptr(a), _ptr(_c128(U)), _ptr(_c128(A)), _ptr(Q), n_tv, _ptr(Dc),
                            None if lst is None else _ptr(lst), nl)
     return Dc
+
+
+def coarse_self_inverse(Dc):
+    """The inverse of every coarse site's self block, [Vc][2N][2N] (numpy's inverse)."""
+    Dc = _c128(Dc)
+    return np.ascontiguousarray(np.linalg.inv(Dc[:, 0]))
+
+
+def coarse_gmres_eo(L, a, Dc, bc, m, tol=0.0, Ainv=None):
+    """Even-odd preconditioned coarse solve (GMRES on the Schur complement over the even
+    coarse sites, then the odd sites): returns (u [n][Vc][2][N], res, iters); res and iters
+    refer to the Schur system."""
+    L, a = _ext(L), _ext(a)
+    Dc = _c128(Dc)
+    bc = _c128(bc)
+    nc = Dc.shape[-1]
+    n = bc.size // (n_aggregates(L, a) * nc)
+    N = nc // 2
+    if Ainv is None:
+        Ainv = coarse_self_inverse(Dc)
+    u = np.zeros_like(bc)
+    res = np.zeros(n)
+    its = np.zeros(n, np.int32)
+    rc = lib().oracle_coarse_gmres_eo(_ptr(L), _ptr(a), _ptr(Dc), _ptr(_c128(Ainv)), N, _ptr(bc), _ptr(u), n, int(m),
+                                      float(tol), _ptr(res), _ptr(its))
+    if rc != 0:
+        raise ValueError("oracle_coarse_gmres_eo: coarse extents must be even")
+    return u, res, its

@@ -930,16 +930,13 @@ void oracle_coarse_apply(const int *L, const int *a, const double *Dc_, int n_tv
  * |g_{j+1}| falls to tol * ||b|| (tol = 0: exactly m iterations, or fewer on breakdown).
  * res_out[k] (nullable) = final |g_J| / ||b||, iters_out[k] (nullable) = J.
  * Coarse vectors [n_rhs][Vc][2 n_tv]. */
-void oracle_coarse_gmres(const int *L, const int *a, const double *Dc_, int n_tv, const double *b_, double *u_,
-                         int n_rhs, int m, double tol, double *res_out, int *iters_out)
+/* one right-hand side of the GMRES described above, for the operator apply(ctx, in, out) on
+ * vectors of dim complex entries */
+typedef void (*coarse_op_fn)(const void *ctx, const cplx *in, cplx *out);
+
+static void gmres_one(long dim, coarse_op_fn apply, const void *ctx, const cplx *b, cplx *u, int m, double tol,
+                      double *res, int *iters)
 {
-    int na[4];
-    block_counts(L, a, na);
-    long Vc = (long)na[0] * na[1] * na[2] * na[3];
-    long dim = Vc * 2 * n_tv;
-    for (int k = 0; k < n_rhs; ++k) {
-        const cplx *b = (const cplx *)b_ + (long)k * dim;
-        cplx *u = (cplx *)u_ + (long)k * dim;
         cplx *Vb = calloc((size_t)(m + 1) * dim, sizeof(cplx));
         cplx *w = malloc(dim * sizeof(cplx));
         cplx *H = calloc((size_t)(m + 1) * m, sizeof(cplx)); /* H[i][j] at i * m + j */
@@ -956,7 +953,7 @@ void oracle_coarse_gmres(const int *L, const int *a, const double *Dc_, int n_tv
             g[0] = beta;
             for (int j = 0; j < m; ++j) {
                 if (!(est > tol * beta)) break;
-                oracle_coarse_apply(L, a, Dc_, n_tv, (const double *)(Vb + (long)j * dim), (double *)w, 1);
+                apply(ctx, Vb + (long)j * dim, w);
                 for (int pass = 0; pass < 2; ++pass) {
                     cplx h[65];
                     for (int i = 0; i <= j; ++i) {
@@ -1008,13 +1005,135 @@ void oracle_coarse_gmres(const int *L, const int *a, const double *Dc_, int n_tv
             for (int i = 0; i < J; ++i)
                 for (long e = 0; e < dim; ++e) u[e] += y[i] * Vb[(long)i * dim + e];
         }
-        if (res_out) res_out[k] = beta > 0 ? est / beta : 0;
-        if (iters_out) iters_out[k] = J;
+        if (res) *res = beta > 0 ? est / beta : 0;
+        if (iters) *iters = J;
         free(Vb);
         free(w);
         free(H);
         free(g);
         free(sn);
         free(cs);
+}
+
+typedef struct {
+    const int *L, *a;
+    const double *Dc;
+    int n_tv;
+} coarse_ctx;
+
+static void dc_apply(const void *ctx_, const cplx *in, cplx *out)
+{
+    const coarse_ctx *c = (const coarse_ctx *)ctx_;
+    oracle_coarse_apply(c->L, c->a, c->Dc, c->n_tv, (const double *)in, (double *)out, 1);
+}
+
+void oracle_coarse_gmres(const int *L, const int *a, const double *Dc_, int n_tv, const double *b_, double *u_,
+                         int n_rhs, int m, double tol, double *res_out, int *iters_out)
+{
+    int na[4];
+    block_counts(L, a, na);
+    long dim = (long)na[0] * na[1] * na[2] * na[3] * 2 * n_tv;
+    coarse_ctx ctx = {L, a, Dc_, n_tv};
+    for (int k = 0; k < n_rhs; ++k)
+        gmres_one(dim, dc_apply, &ctx, (const cplx *)b_ + (long)k * dim, (cplx *)u_ + (long)k * dim, m, tol,
+                  res_out ? res_out + k : NULL, iters_out ? iters_out + k : NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Even-odd preconditioned coarse solve                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Coarse sites split by the parity of their coordinate sum.  With every coarse extent even,
+ * each of the 8 hop blocks joins sites of opposite parity, so in (even, odd) order
+ * D_c = [[A_ee, H_eo], [H_oe, A_oo]], A the self blocks and H the hop blocks: H_oe v_e is the
+ * odd part of D_c (v_e, 0) and H_eo u_o the even part of D_c (0, u_o).  Ainv: [Vc][2 n_tv]^2,
+ * the inverse of each self block (only the odd sites' are used). */
+typedef struct {
+    coarse_ctx c;
+    const cplx *Ainv;
+    long Vc;
+    int nc;
+    const int *par;
+    cplx *t1, *t2;
+} eo_coarse_ctx;
+
+/* out = in on the sites of parity p, 0 on the others */
+static void keep_coarse_parity(const eo_coarse_ctx *e, int p, const cplx *in, cplx *out)
+{
+    for (long i = 0; i < e->Vc; ++i)
+        for (int r = 0; r < e->nc; ++r) out[i * e->nc + r] = e->par[i] == p ? in[i * e->nc + r] : 0;
+}
+
+/* out = A_oo^-1 in on the odd sites, 0 on the even ones */
+static void odd_self_inverse(const eo_coarse_ctx *e, const cplx *in, cplx *out)
+{
+    int nc = e->nc;
+    for (long i = 0; i < e->Vc; ++i) {
+        for (int r = 0; r < nc; ++r) {
+            cplx s = 0;
+            if (e->par[i] == 1)
+                for (int c = 0; c < nc; ++c) s += e->Ainv[(i * nc + r) * nc + c] * in[i * nc + c];
+            out[i * nc + r] = s;
+        }
     }
+}
+
+/* out = S v = A_ee v_e - H_eo A_oo^-1 H_oe v_e on the even sites, 0 on the odd ones */
+static void schur_coarse_apply(const void *ctx_, const cplx *in, cplx *out)
+{
+    const eo_coarse_ctx *e = (const eo_coarse_ctx *)ctx_;
+    long dim = e->Vc * e->nc;
+    keep_coarse_parity(e, 0, in, e->t1);
+    dc_apply(&e->c, e->t1, e->t2);         /* (A_ee v_e, H_oe v_e) */
+    odd_self_inverse(e, e->t2, e->t1);     /* (0, A_oo^-1 H_oe v_e) */
+    dc_apply(&e->c, e->t1, out);           /* even part: H_eo A_oo^-1 H_oe v_e */
+    for (long x = 0; x < dim; ++x) out[x] = e->t2[x] - out[x];
+    keep_coarse_parity(e, 0, out, out);
+}
+
+/* u ~ D_c^-1 b through the Schur complement: bhat_e = b_e - H_eo A_oo^-1 b_o, GMRES (gmres_one,
+ * m iterations, tolerance tol relative to ||bhat_e||) on S u_e = bhat_e from zero, then
+ * u_o = A_oo^-1 (b_o - H_oe u_e).  res_out / iters_out as in oracle_coarse_gmres, for the Schur
+ * system.  Returns -2 if a coarse extent is odd. */
+int oracle_coarse_gmres_eo(const int *L, const int *a, const double *Dc_, const double *Ainv_, int n_tv,
+                           const double *b_, double *u_, int n_rhs, int m, double tol, double *res_out,
+                           int *iters_out)
+{
+    int na[4];
+    block_counts(L, a, na);
+    for (int mu = 0; mu < 4; ++mu)
+        if (na[mu] % 2) return -2;
+    long Vc = (long)na[0] * na[1] * na[2] * na[3];
+    int nc = 2 * n_tv;
+    long dim = Vc * nc;
+    int *par = malloc(Vc * sizeof(int));
+    for (long i = 0; i < Vc; ++i) {
+        int c[4];
+        site_coords(na, i, c);
+        par[i] = (c[0] + c[1] + c[2] + c[3]) & 1;
+    }
+    eo_coarse_ctx e = {{L, a, Dc_, n_tv}, (const cplx *)Ainv_, Vc, nc, par, malloc(dim * sizeof(cplx)),
+                       malloc(dim * sizeof(cplx))};
+    cplx *bh = malloc(dim * sizeof(cplx)), *t = malloc(dim * sizeof(cplx)), *t2 = malloc(dim * sizeof(cplx));
+    for (int k = 0; k < n_rhs; ++k) {
+        const cplx *b = (const cplx *)b_ + (long)k * dim;
+        cplx *u = (cplx *)u_ + (long)k * dim;
+        odd_self_inverse(&e, b, t);          /* (0, A_oo^-1 b_o) */
+        dc_apply(&e.c, t, t2);               /* even part: H_eo A_oo^-1 b_o */
+        for (long x = 0; x < dim; ++x) bh[x] = b[x] - t2[x];
+        keep_coarse_parity(&e, 0, bh, bh);
+        gmres_one(dim, schur_coarse_apply, &e, bh, u, m, tol, res_out ? res_out + k : NULL,
+                  iters_out ? iters_out + k : NULL);
+        dc_apply(&e.c, u, t2);               /* odd part: H_oe u_e */
+        for (long x = 0; x < dim; ++x) t[x] = b[x] - t2[x];
+        odd_self_inverse(&e, t, t2);         /* (0, A_oo^-1 (b_o - H_oe u_e)) */
+        for (long x = 0; x < dim; ++x) u[x] += t2[x];
+    }
+    free(par);
+    free(e.t1);
+    free(e.t2);
+    free(bh);
+    free(t);
+    free(t2);
+    return 0;
 }
