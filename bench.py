@@ -312,9 +312,33 @@ def refinement_bench(mr, m=8, tol=0.05, reps=10):
     y1 = op.empty(1)
     t_r1 = time_call(lambda: [mrhs.restrict_mrhs(op.handle, mr.Q, D32, n, y1, op.dtype, b1, 1) for _ in range(n)],
                      max(2, reps // 4))
+    # the true relative residual ||b - D_c u|| / ||b|| per right-hand side of a coarse solution
+    zc = op.coarse_empty(n, n)
+
+    def true_res(u):
+        mrhs.coarse_apply_mrhs(op.handle, mr.Dc, n, u, zc, n)
+        ldc = (n + 3) // 4 * 4
+        r = (bc - zc).view(-1, ldc).double()
+        return float((r.pow(2).sum(0).sqrt() / bc.view(-1, ldc).double().pow(2).sum(0).sqrt())[:n].max().item())
+
+    mrhs.coarse_solve_mrhs(op.handle, mr.Dc, n, bc, uc, n, m, tol, gws, res, its)
+    true_plain = true_res(uc)
+    # even-odd preconditioned coarse solve on the same system (GMRES on the even-site Schur
+    # complement; the coarse extents 16 / 4 = 4 are even)
+    Dinv = torch.empty(op.n_agg * (2 * n) ** 2 * 2, dtype=torch.float32, device="cuda")
+    t_inv = time_call(lambda: mrhs.coarse_self_invert(op.handle, mr.Dc, n, Dinv), reps)
+    its_eo = torch.zeros(n, dtype=torch.int32, device="cuda")
+    res_eo = torch.zeros(n, dtype=torch.float64, device="cuda")
+    gws_eo = torch.empty(mrhs.mrhs_coarse_solve_eo_workspace_bytes(op.handle, n, n, m), dtype=torch.uint8, device="cuda")
+    t_cs_eo = time_call(lambda: mrhs.coarse_solve_eo_mrhs(op.handle, mr.Dc, Dinv, n, bc, uc, n, m, tol, gws_eo, res_eo,
+                                                          its_eo), reps)
+    true_eo = true_res(uc)
     torch.cuda.synchronize()
     return {"gmres_max_iter": m, "tol": tol, "iterations_needed": int(its.max().item()),
-            "coarse_residual_max": float(res.max().item()),
+            "coarse_residual_max": float(res.max().item()), "coarse_true_residual_max": true_plain,
+            "coarse_solve_eo_ms": round(t_cs_eo, 4), "coarse_self_invert_ms": round(t_inv, 4),
+            "eo_iterations_needed": int(its_eo.max().item()), "eo_schur_residual_max": float(res_eo.max().item()),
+            "eo_true_residual_max": true_eo,
             "refine_ms": round(t_refine, 4), "refine_pass_with_rebuild_ms": round(t_pass, 4),
             "refine_site_rhs_per_s": int(np.prod(L)) * n * N_SAP / (t_pass * 1e-3),
             "coarse_solve_mrhs_ms": round(t_cs, 4), "coarse_solve_srhs_looped_ms": round(t_cs1, 4),

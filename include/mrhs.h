@@ -196,6 +196,24 @@ int coarse_solve_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const fl
                       int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* Even-odd preconditioned coarse solve (the coarse-grid counterpart of DD-alpha-AMG's even-odd
+ * preconditioning).  Coarse sites split by the parity of their coordinate sum; every coarse
+ * extent L/agg must be even, so each of the 8 hop blocks joins sites of opposite parity:
+ * D_c = [[A_ee, H_eo], [H_oe, A_oo]] with A the self blocks.  With bhat_e = b_e - H_eo A_oo^-1 b_o,
+ * GMRES as in coarse_solve_mrhs (m iterations, tolerance tol relative to ||bhat_e||) runs on
+ * the Schur complement S = A_ee - H_eo A_oo^-1 H_oe for S u_e = bhat_e from zero, and then
+ * u_o = A_oo^-1 (b_o - H_oe u_e); res_out and iters_out refer to the Schur system.
+ * coarse_self_invert: Dinv [Vc][2 n_tv][2 n_tv] complex64 (DEVICE), the inverse of every site's
+ * self block by FP64 Gauss-Jordan elimination with partial pivoting; status (DEVICE int32,
+ * nullable) receives 0, or 1 + the lowest site whose block has no non-zero pivot (its Dinv is
+ * zero).  Errors: EUNSUPPORTED for an odd coarse extent or n_tv > 32; overlaps as for
+ * coarse_solve_mrhs.  ws: at least mrhs_coarse_solve_eo_workspace_bytes bytes. */
+int coarse_self_invert(const mrhs_op *op, const float *Dc, int32_t n_tv, float *Dinv, int32_t *status, void *stream);
+size_t mrhs_coarse_solve_eo_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m);
+int coarse_solve_eo_mrhs(const mrhs_op *op, const float *Dc, const float *Dinv, int32_t n_tv, const float *bc, float *uc,
+                         int32_t n_rhs, int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws,
+                         size_t ws_bytes, void *stream);
+
 /* One pass of the refinement phase over all test vectors at once (Alg. 2 with the block
  * length N_b = n_tv, Alg. 1's loop body for every vector): v_c = R v, u_c ~ D_c^-1 v_c
  * (coarse_solve_mrhs: m iterations, tolerance tol), u = P u_c, then x = SAP(v) started

@@ -460,6 +460,46 @@ int coarse_solve_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const fl
     return launch_coarse_solve(op, Dc, n_tv, bc, uc, n_rhs, m, tol, res_out, iters_out, ws, (hipStream_t)stream);
 }
 
+int coarse_self_invert(const mrhs_op *op, const float *Dc, int32_t n_tv, float *Dinv, int32_t *status, void *stream)
+{
+    if (int rc = check_op(op)) return rc;
+    if (n_tv < 1 || n_tv > 32) return set_error(MRHS_EUNSUPPORTED, "n_tv must be 1..32");
+    if (!Dc || !Dinv) return set_error(MRHS_EINVAL, "null argument");
+    const size_t n2 = (size_t)4 * n_tv * n_tv;
+    if (ranges_overlap(Dinv, (size_t)op->n_agg * n2 * 2 * sizeof(float), Dc, (size_t)op->n_agg * 9 * n2 * 2 * sizeof(float)))
+        return set_error(MRHS_EINVAL, "Dinv overlaps D_c");
+    return launch_coarse_self_inverse(op, Dc, n_tv, Dinv, status, (hipStream_t)stream);
+}
+
+size_t mrhs_coarse_solve_eo_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m)
+{
+    if (!op || n_tv <= 0 || n_rhs <= 0 || m <= 0) return 0;
+    return ws_bytes_coarse_solve_eo(op, n_tv, n_rhs, m);
+}
+
+int coarse_solve_eo_mrhs(const mrhs_op *op, const float *Dc, const float *Dinv, int32_t n_tv, const float *bc, float *uc,
+                         int32_t n_rhs, int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, MRHS_DTYPE_F32)) return rc;
+    if (!Dc || !Dinv || !bc || !uc) return set_error(MRHS_EINVAL, "null argument");
+    for (int mu = 0; mu < 4; ++mu)
+        if (op->na[mu] % 2)
+            return set_error(MRHS_EUNSUPPORTED, "the even-odd coarse solve needs an even coarse extent in every direction");
+    if (m < 1 || m > 64) return set_error(MRHS_EINVAL, "iteration count must be 1..64");
+    if (!(tol >= 0.0)) return set_error(MRHS_EINVAL, "tolerance must be >= 0");
+    const size_t need = ws_bytes_coarse_solve_eo(op, n_tv, n_rhs, m);
+    if (!ws || ws_bytes < need) return set_error(MRHS_EINVAL, "workspace too small");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    const size_t n2 = (size_t)4 * n_tv * n_tv;
+    if (ranges_overlap(uc, cb, bc, cb) || ranges_overlap(uc, cb, ws, need) || ranges_overlap(bc, cb, ws, need) ||
+        ranges_overlap(uc, cb, Dc, (size_t)op->n_agg * 9 * n2 * 2 * sizeof(float)) ||
+        ranges_overlap(uc, cb, Dinv, (size_t)op->n_agg * n2 * 2 * sizeof(float)))
+        return set_error(MRHS_EINVAL, "coarse vectors overlap each other, D_c, Dinv or the workspace");
+    return launch_coarse_solve_eo(op, Dc, Dinv, n_tv, bc, uc, n_rhs, m, tol, res_out, iters_out, ws,
+                                  (hipStream_t)stream);
+}
+
 size_t mrhs_refine_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t m)
 {
     if (!op || n_tv <= 0 || m <= 0) return 0;

@@ -10,6 +10,7 @@
 // zero and its Hessenberg matrix is frozen), so the host issues a fixed sequence of
 // launches without reading anything back.
 #include <algorithm>
+#include <climits>
 
 #include "launch.h"
 
@@ -317,16 +318,104 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
     return off;
 }
 
-}  // namespace
-
-size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m) { return gm_layout(op, n_tv, n, m, nullptr, nullptr); }
-
-int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
-                        double *res_out, int32_t *iters_out, void *ws, hipStream_t st)
+// Inverse of every coarse site's self block (2N x 2N complex): Gauss-Jordan elimination with
+// partial (row) pivoting, in place in LDS in FP64, one workgroup per coarse site; the row
+// exchanges are undone as column exchanges at the end.  A block without a non-zero pivot gives
+// zeros and status = 1 + the lowest such site (status preset to INT_MAX, mapped to 0 after).
+__global__ void __launch_bounds__(256) k_coarse_self_inverse(const float *__restrict__ Dc, float *__restrict__ Dinv,
+                                                             int N2, int *status)
 {
-    GmArgs a{};
-    gm_layout(op, n_tv, n, m, (char *)ws, &a);
-    a.tol = tol;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *M = reinterpret_cast<double2 *>(smem);  // [N2][N2]
+    double2 *f = M + N2 * N2;                          // column factors [N2]
+    int *perm = reinterpret_cast<int *>(f + N2);       // [N2]
+    __shared__ int piv, singular;
+    const int i = blockIdx.x, tid = threadIdx.x, bd = blockDim.x, n2 = N2 * N2;
+    const float *blk = Dc + (size_t)i * 9 * n2 * 2;  // block 0: self
+    for (int e = tid; e < n2; e += bd) M[e] = make_double2(blk[2 * e], blk[2 * e + 1]);
+    if (tid == 0) singular = 0;
+    __syncthreads();
+    for (int k = 0; k < N2; ++k) {
+        if (tid == 0) {
+            int p = k;
+            double best = M[k * N2 + k].x * M[k * N2 + k].x + M[k * N2 + k].y * M[k * N2 + k].y;
+            for (int r = k + 1; r < N2; ++r) {
+                const double2 v = M[r * N2 + k];
+                const double mg = v.x * v.x + v.y * v.y;
+                if (mg > best) {
+                    best = mg;
+                    p = r;
+                }
+            }
+            perm[k] = p;
+            piv = p;
+            if (!(best > 0.0) || !isfinite(best)) singular = 1;
+        }
+        __syncthreads();
+        if (singular) break;  // shared: every thread leaves together
+        const int p = piv;
+        if (p != k)
+            for (int j = tid; j < N2; j += bd) {
+                const double2 t = M[k * N2 + j];
+                M[k * N2 + j] = M[p * N2 + j];
+                M[p * N2 + j] = t;
+            }
+        __syncthreads();
+        const double2 pv = M[k * N2 + k];
+        const double den = pv.x * pv.x + pv.y * pv.y, ir = pv.x / den, ii = -pv.y / den;  // 1 / pivot
+        for (int r = tid; r < N2; r += bd) f[r] = M[r * N2 + k];
+        __syncthreads();
+        // row k: (row k with a_kk = 1) / pivot
+        for (int j = tid; j < N2; j += bd) {
+            const double2 x = j == k ? make_double2(1.0, 0.0) : M[k * N2 + j];
+            M[k * N2 + j] = make_double2(x.x * ir - x.y * ii, x.x * ii + x.y * ir);
+        }
+        __syncthreads();
+        // other rows: (row r with a_rk = 0) - f_r row k
+        for (int e = tid; e < n2; e += bd) {
+            const int r = e / N2, j = e - r * N2;
+            if (r == k) continue;
+            double2 x = j == k ? make_double2(0.0, 0.0) : M[e];
+            const double2 fr = f[r], y = M[k * N2 + j];
+            x.x -= fr.x * y.x - fr.y * y.y;
+            x.y -= fr.x * y.y + fr.y * y.x;
+            M[e] = x;
+        }
+        __syncthreads();
+    }
+    float *out = Dinv + (size_t)i * n2 * 2;
+    if (singular) {
+        for (int e = tid; e < 2 * n2; e += bd) out[e] = 0.f;
+        if (tid == 0 && status) atomicMin(status, i + 1);
+        return;
+    }
+    for (int k = N2 - 1; k >= 0; --k) {
+        const int p = perm[k];
+        if (p != k)
+            for (int r = tid; r < N2; r += bd) {
+                const double2 t = M[r * N2 + k];
+                M[r * N2 + k] = M[r * N2 + p];
+                M[r * N2 + p] = t;
+            }
+        __syncthreads();
+    }
+    for (int e = tid; e < n2; e += bd) {
+        out[2 * e] = (float)M[e].x;
+        out[2 * e + 1] = (float)M[e].y;
+    }
+}
+
+__global__ void k_inv_status_init(int *s) { *s = INT_MAX; }
+__global__ void k_inv_status_final(int *s)
+{
+    if (*s == INT_MAX) *s = 0;
+}
+
+// GMRES on all right-hand sides for the operator apply(in, out) (coarse vectors), from b into u
+template <typename Apply>
+int gmres_run(GmArgs &a, const float *b, float *u, int m, double *res_out, int32_t *iters_out, Apply apply,
+              hipStream_t st)
+{
     const long nel = a.dim * a.ldc;
     const int eb = (int)((nel + GTHR - 1) / GTHR);
     const int kb = (a.ldc + 63) / 64;
@@ -345,7 +434,7 @@ int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const floa
     GM_CHECK("k_gm_scale launch");
     for (int j = 0; j < m; ++j) {
         float *vj = a.V + (long)j * a.cvlen;
-        if (int rc = launch_coarse_apply(op, Dc, n_tv, vj, a.w, n, st)) return rc;
+        if (int rc = apply((const float *)vj, a.w)) return rc;
         for (int pass = 0; pass < 2; ++pass) {
             if (int rc = dots(a.V, a.cvlen, j + 1, a.w, j, GM_PROJECT)) return rc;
             hipLaunchKernelGGL(k_gm_axpy, dim3(eb), dim3(GTHR), 0, st, a, j + 1);
@@ -361,4 +450,89 @@ int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const floa
     GM_CHECK("k_gm_combine launch");
 #undef GM_CHECK
     return MRHS_OK;
+}
+
+size_t cvec_bytes(const mrhs_op *op, int n_tv, int n)
+{
+    return align256((size_t)op->n_agg * 2 * n_tv * 2 * ((n + 3) / 4 * 4) * sizeof(float));
+}
+
+}  // namespace
+
+size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m) { return gm_layout(op, n_tv, n, m, nullptr, nullptr); }
+
+int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
+                        double *res_out, int32_t *iters_out, void *ws, hipStream_t st)
+{
+    GmArgs a{};
+    gm_layout(op, n_tv, n, m, (char *)ws, &a);
+    a.tol = tol;
+    auto apply = [&](const float *in, float *out) { return launch_coarse_apply(op, Dc, n_tv, in, out, n, st); };
+    return gmres_run(a, b, u, m, res_out, iters_out, apply, st);
+}
+
+size_t ws_bytes_coarse_solve_eo(const mrhs_op *op, int n_tv, int n, int m)
+{
+    return gm_layout(op, n_tv, n, m, nullptr, nullptr) + 3 * cvec_bytes(op, n_tv, n);
+}
+
+size_t coarse_inverse_lds_bytes(int n_tv)
+{
+    const size_t N2 = 2 * (size_t)n_tv;
+    return N2 * N2 * sizeof(double2) + N2 * sizeof(double2) + N2 * sizeof(int);
+}
+
+int launch_coarse_self_inverse(const mrhs_op *op, const float *Dc, int n_tv, float *Dinv, int32_t *status,
+                               hipStream_t st)
+{
+    const size_t lds = coarse_inverse_lds_bytes(n_tv);
+    static size_t done = 0;
+    if (lds > 65536 && lds > done) {
+        if (int rc = hip_check(hipFuncSetAttribute((const void *)k_coarse_self_inverse,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                               "hipFuncSetAttribute(coarse self inverse LDS)"))
+            return rc;
+        done = lds;
+    }
+    if (status) {
+        hipLaunchKernelGGL(k_inv_status_init, dim3(1), dim3(1), 0, st, status);
+        if (int rc = hip_check(hipGetLastError(), "k_inv_status_init launch")) return rc;
+    }
+    hipLaunchKernelGGL(k_coarse_self_inverse, dim3(op->n_agg), dim3(256), lds, st, Dc, Dinv, 2 * n_tv, status);
+    if (int rc = hip_check(hipGetLastError(), "k_coarse_self_inverse launch")) return rc;
+    if (status) {
+        hipLaunchKernelGGL(k_inv_status_final, dim3(1), dim3(1), 0, st, status);
+        if (int rc = hip_check(hipGetLastError(), "k_inv_status_final launch")) return rc;
+    }
+    return MRHS_OK;
+}
+
+// The even-odd preconditioned coarse solve.  Coarse sites split by the parity of their
+// coordinate sum (every coarse extent even, so each hop block joins opposite parities):
+// D_c = [[A_ee, H_eo], [H_oe, A_oo]] with A the self blocks.  bhat_e = b_e - H_eo A_oo^-1 b_o;
+// GMRES on S u_e = bhat_e, S = A_ee - H_eo A_oo^-1 H_oe (coarse vectors whose odd sites stay
+// zero); u_o = A_oo^-1 (b_o - H_oe u_e).  Dinv: the self-block inverses (launch_coarse_self_inverse).
+int launch_coarse_solve_eo(const mrhs_op *op, const float *Dc, const float *Dinv, int n_tv, const float *b, float *u,
+                           int n, int m, double tol, double *res_out, int32_t *iters_out, void *ws, hipStream_t st)
+{
+    GmArgs a{};
+    const size_t gmb = gm_layout(op, n_tv, n, m, (char *)ws, &a);
+    a.tol = tol;
+    const size_t cb = cvec_bytes(op, n_tv, n);
+    float *bh = (float *)((char *)ws + gmb), *t1 = (float *)((char *)ws + gmb + cb), *t2 = (float *)((char *)ws + gmb + 2 * cb);
+    auto ap = [&](const float *D, int nblk, const float *y0, const float *ys, const float *yh, float sh, int par, bool zero,
+                  float *out) { return launch_coarse_apply_ex(op, D, nblk, n_tv, y0, ys, yh, sh, par, zero, out, n, st); };
+    // bhat = b - H (A_oo^-1 b_o) on the even sites, 0 on the odd ones
+    if (int rc = ap(Dinv, 1, nullptr, b, nullptr, 1.f, 1, true, t1)) return rc;
+    if (int rc = ap(Dc, 9, b, nullptr, t1, -1.f, 0, true, bh)) return rc;
+    // S v = A v - H (A_oo^-1 (H v)_o) on the even sites
+    auto schur = [&](const float *in, float *out) {
+        if (int rc = ap(Dc, 9, nullptr, nullptr, in, 1.f, 1, true, t1)) return rc;
+        if (int rc = ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, true, t2)) return rc;
+        return ap(Dc, 9, nullptr, in, t2, -1.f, 0, true, out);
+    };
+    if (int rc = gmres_run(a, bh, u, m, res_out, iters_out, schur, st)) return rc;
+    // u_o = A_oo^-1 (b - H u)_o, the even sites of u kept
+    if (int rc = ap(Dc, 9, b, nullptr, u, -1.f, 1, true, t1)) return rc;
+    return ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, false, u);
 }

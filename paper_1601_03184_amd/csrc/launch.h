@@ -32,7 +32,19 @@ int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const fl
                    hipStream_t st);
 int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,
                         hipStream_t st);
+// the general form: yco = y0 + D_self yself + s_hop * sum_d D_d yhop(nbr_d) with D = Dc[site][0..nblk),
+// on every coarse site (parity -1) or those of one parity (the others zeroed or left untouched);
+// null inputs drop their terms
+int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
+                           const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
+                           hipStream_t st);
 size_t transfer_lds_bytes(const mrhs_op *op);
+// even-odd preconditioned coarse solve and the self-block inverses it uses
+size_t ws_bytes_coarse_solve_eo(const mrhs_op *op, int n_tv, int n, int m);
+int launch_coarse_self_inverse(const mrhs_op *op, const float *Dc, int n_tv, float *Dinv, int32_t *status,
+                               hipStream_t st);
+int launch_coarse_solve_eo(const mrhs_op *op, const float *Dc, const float *Dinv, int n_tv, const float *b, float *u,
+                           int n, int m, double tol, double *res_out, int32_t *iters_out, void *ws, hipStream_t st);
 size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m);
 int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
                         double *res_out, int32_t *iters_out, void *ws, hipStream_t st);

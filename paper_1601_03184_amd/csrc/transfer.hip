@@ -246,8 +246,14 @@ __global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
 struct CApplyArgs {
     int na[4];
     int Vc, N, n, ldc;
-    const float *Dc;  // [Vc][9][2N][2N][2]
-    const float *yc;
+    const float *Dc;     // [Vc][nblk][2N][2N][2]
+    int nblk;            // 9 (self, +x..+t, -x..-t) or 1 (self only)
+    const float *yself;  // input of the self block (null: no self term)
+    const float *yhop;   // input of the 8 hop blocks (null: no hop term)
+    const float *y0;     // added to the result (nullable)
+    float s_hop;         // sign of the hop term
+    int parity;          // -1: every coarse site; 0 / 1: only the sites of that parity
+    int zero_other;      // the other sites' output: 1 written as zero, 0 left untouched
     float *yco;
 };
 
@@ -271,44 +277,67 @@ template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CA
     const int row = 16 * tr + (lane & 15), k = 16 * tk + (lane & 15);
     const int rows_here = N2 - 16 * tr < 16 ? N2 - 16 * tr : 16;
     const bool rok = row < N2, kok = k < a.n;
+    float *out = a.yco + (size_t)i * N2 * 2 * a.ldc;
+    if (a.parity >= 0 && ((c[0] + c[1] + c[2] + c[3]) & 1) != a.parity) {
+        // a site of the other parity (uniform over the workgroup, before any barrier)
+        if (a.zero_other && g == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int orow = 16 * tr + 4 * (lane >> 4) + q;
+                if (orow < N2 && k < a.ldc) {
+                    out[(size_t)(2 * orow) * a.ldc + k] = 0.f;
+                    out[(size_t)(2 * orow + 1) * a.ldc + k] = 0.f;
+                }
+            }
+        return;
+    }
     f4 dr = {0.f, 0.f, 0.f, 0.f}, di = {0.f, 0.f, 0.f, 0.f};
     float *sl = slab[g];
-    for (int d = g; d < 9; d += CA_GROUPS) {
+    // the same number of rounds (and barriers) for every group
+    for (int it = 0; it < (a.nblk + CA_GROUPS - 1) / CA_GROUPS; ++it) {
+        const int d = g + CA_GROUPS * it;
+        const float *ysrc = d == 0 ? a.yself : a.yhop;
+        const bool use = d < a.nblk && ysrc != nullptr;  // uniform over the group
+        const float sgn = d == 0 ? 1.f : a.s_hop;
         int cn[4] = {c[0], c[1], c[2], c[3]};
         if (d >= 1 && d <= 4) cn[d - 1] = (cn[d - 1] + 1) % a.na[d - 1];
-        if (d >= 5) cn[d - 5] = (cn[d - 5] - 1 + a.na[d - 5]) % a.na[d - 5];
+        if (d >= 5 && d <= 8) cn[d - 5] = (cn[d - 5] - 1 + a.na[d - 5]) % a.na[d - 5];
         const int j = cn[0] + a.na[0] * (cn[1] + a.na[1] * (cn[2] + a.na[2] * cn[3]));
-        const float *blk = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2 + (size_t)16 * tr * N2 * 2;
-        const float *yj = a.yc + (size_t)j * N2 * 2 * a.ldc;
-        // the 16-row slab of the block (contiguous) into LDS
-        const int nq = rows_here * a.N;  // float4 per row: 2 N2 / 4 = N
-        for (int q = tk * 64 + lane; q < nq; q += 64 * TK) {
-            const int rr = q / a.N, c4 = q - rr * a.N;
-            const float4 v = ((const float4 *)blk)[q];
-            *(float2 *)&sl[rr * RS + 4 * c4] = make_float2(v.x, v.y);
-            *(float2 *)&sl[rr * RS + 4 * c4 + 2] = make_float2(v.z, v.w);
-        }
         float br[KS], bi[KS];
+        if (use) {
+            const float *blk = a.Dc + ((size_t)i * a.nblk + d) * N2 * N2 * 2 + (size_t)16 * tr * N2 * 2;
+            const float *yj = ysrc + (size_t)j * N2 * 2 * a.ldc;
+            // the 16-row slab of the block (contiguous) into LDS
+            const int nq = rows_here * a.N;  // float4 per row: 2 N2 / 4 = N
+            for (int q = tk * 64 + lane; q < nq; q += 64 * TK) {
+                const int rr = q / a.N, c4 = q - rr * a.N;
+                const float4 v = ((const float4 *)blk)[q];
+                *(float2 *)&sl[rr * RS + 4 * c4] = make_float2(v.x, v.y);
+                *(float2 *)&sl[rr * RS + 4 * c4 + 2] = make_float2(v.z, v.w);
+            }
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int col = 4 * ks + (lane >> 4);
-            const bool bok = kok && col < N2;
-            const size_t ib = bok ? (size_t)(2 * col) * a.ldc + k : 0;
-            const float b0 = yj[ib], b1 = yj[bok ? ib + a.ldc : 0];
-            br[ks] = bok ? b0 : 0.f;
-            bi[ks] = bok ? b1 : 0.f;
+            for (int ks = 0; ks < KS; ++ks) {
+                const int col = 4 * ks + (lane >> 4);
+                const bool bok = kok && col < N2;
+                const size_t ib = bok ? (size_t)(2 * col) * a.ldc + k : 0;
+                const float b0 = yj[ib], b1 = yj[bok ? ib + a.ldc : 0];
+                br[ks] = bok ? sgn * b0 : 0.f;
+                bi[ks] = bok ? sgn * b1 : 0.f;
+            }
         }
         __syncthreads();
+        if (use) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const int col = 4 * ks + (lane >> 4);
-            const bool aok = rok && col < N2;
-            const float2 v = *(const float2 *)&sl[(aok ? (lane & 15) * RS + 2 * col : 0)];
-            const float xr = aok ? v.x : 0.f, xi = aok ? v.y : 0.f;
-            dr = mfma32(xr, br[ks], dr);
-            dr = mfma32(-xi, bi[ks], dr);
-            di = mfma32(xr, bi[ks], di);
-            di = mfma32(xi, br[ks], di);
+            for (int ks = 0; ks < KS; ++ks) {
+                const int col = 4 * ks + (lane >> 4);
+                const bool aok = rok && col < N2;
+                const float2 v = *(const float2 *)&sl[(aok ? (lane & 15) * RS + 2 * col : 0)];
+                const float xr = aok ? v.x : 0.f, xi = aok ? v.y : 0.f;
+                dr = mfma32(xr, br[ks], dr);
+                dr = mfma32(-xi, bi[ks], dr);
+                di = mfma32(xr, bi[ks], di);
+                di = mfma32(xi, br[ks], di);
+            }
         }
         __syncthreads();
     }
@@ -323,13 +352,15 @@ template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CA
         dr += part[q][tk][0][lane];
         di += part[q][tk][1][lane];
     }
-    float *out = a.yco + (size_t)i * N2 * 2 * a.ldc;
+    const float *o0 = a.y0 ? a.y0 + (size_t)i * N2 * 2 * a.ldc : nullptr;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int orow = 16 * tr + 4 * (lane >> 4) + q;
         if (orow < N2 && k < a.ldc) {
-            out[(size_t)(2 * orow) * a.ldc + k] = kok ? dr[q] : 0.f;
-            out[(size_t)(2 * orow + 1) * a.ldc + k] = kok ? di[q] : 0.f;
+            const size_t e = (size_t)(2 * orow) * a.ldc + k;
+            const float ar = o0 ? o0[e] : 0.f, ai = o0 ? o0[e + a.ldc] : 0.f;
+            out[e] = kok ? ar + dr[q] : 0.f;
+            out[e + a.ldc] = kok ? ai + di[q] : 0.f;
         }
     }
 }
@@ -417,6 +448,13 @@ int launch_prolong(const mrhs_op *op, const void *Q, int qdt, int n_tv, const fl
 int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const float *yc, float *yco, int n,
                         hipStream_t st)
 {
+    return launch_coarse_apply_ex(op, Dc, 9, n_tv, nullptr, yc, yc, 1.f, -1, false, yco, n, st);
+}
+
+int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
+                           const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
+                           hipStream_t st)
+{
     CApplyArgs a{};
     for (int mu = 0; mu < 4; ++mu) a.na[mu] = op->na[mu];
     a.Vc = op->n_agg;
@@ -424,7 +462,13 @@ int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const floa
     a.n = n;
     a.ldc = (n + 3) / 4 * 4;
     a.Dc = Dc;
-    a.yc = yc;
+    a.nblk = nblk;
+    a.yself = yself;
+    a.yhop = yhop;
+    a.y0 = y0;
+    a.s_hop = s_hop;
+    a.parity = parity;
+    a.zero_other = zero_other ? 1 : 0;
     a.yco = yco;
     if (n_tv < 1 || n_tv > 32 || n < 1 || n > 32) return set_error(MRHS_EUNSUPPORTED, "coarse apply: n_tv and n must be 1..32");
     return coarse_apply_ks<1>(a, (2 * n_tv + 3) / 4, st);

@@ -66,6 +66,9 @@ def lib():
             "coarse_apply_mrhs": (i32, [p, p, i32, p, p, i32, p]),
             "mrhs_coarse_solve_workspace_bytes": (sz, [p, i32, i32, i32]),
             "coarse_solve_mrhs": (i32, [p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
+            "coarse_self_invert": (i32, [p, p, i32, p, p, p]),
+            "mrhs_coarse_solve_eo_workspace_bytes": (sz, [p, i32, i32, i32]),
+            "coarse_solve_eo_mrhs": (i32, [p, p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
             "mrhs_refine_workspace_bytes": (sz, [p, i32, i32]),
             "setup_refine_mrhs": (i32, [p, p, i32, p, i32, p, i32, i32, i32, d, p, sz, p]),
             "mrhs_last_error": (ctypes.c_char_p, []),
@@ -198,6 +201,20 @@ def coarse_solve_mrhs(op, Dc, n_tv, bc, uc, n_rhs, m, tol, ws, res_out=None, ite
     nb = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().coarse_solve_mrhs(op, _dptr(Dc), int(n_tv), _dptr(bc), _dptr(uc), int(n_rhs), int(m), float(tol),
                                    _dptr(res_out), _dptr(iters_out), _dptr(ws), nb, _stream(stream)))
+
+
+def coarse_self_invert(op, Dc, n_tv, Dinv, status=None, stream=None):
+    _check(lib().coarse_self_invert(op, _dptr(Dc), int(n_tv), _dptr(Dinv), _dptr(status), _stream(stream)))
+
+
+def mrhs_coarse_solve_eo_workspace_bytes(op, n_tv, n_rhs, m):
+    return lib().mrhs_coarse_solve_eo_workspace_bytes(op, int(n_tv), int(n_rhs), int(m))
+
+
+def coarse_solve_eo_mrhs(op, Dc, Dinv, n_tv, bc, uc, n_rhs, m, tol, ws, res_out=None, iters_out=None, stream=None):
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().coarse_solve_eo_mrhs(op, _dptr(Dc), _dptr(Dinv), int(n_tv), _dptr(bc), _dptr(uc), int(n_rhs), int(m),
+                                      float(tol), _dptr(res_out), _dptr(iters_out), _dptr(ws), nb, _stream(stream)))
 
 
 def mrhs_refine_workspace_bytes(op, n_tv, m):

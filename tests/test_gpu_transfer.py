@@ -189,6 +189,79 @@ def test_coarse_gmres_parity(L, block, agg, prec, S, n_tv, n, m, tol):
     op.close()
 
 
+EO_GMRES_CASES = [
+    # (L, block, agg, prec, S, n_tv, n, m, tol): every coarse extent even
+    ([8, 8, 8, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, 13, 8, 0.0),
+    ([8, 8, 8, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, 20, 30, 0.05),
+    ([4, 4, 4, 4], [2, 2, 2, 2], [2, 2, 2, 2], F32, 4, 4, 3, 6, 0.0),
+    ([4, 4, 4, 4], [2, 2, 2, 2], [2, 2, 2, 2], F32, 4, 32, 32, 4, 0.0),   # 64 x 64 self blocks
+]
+
+
+@pytest.mark.parametrize("L,block,agg,prec,S,n_tv,n,m,tol", EO_GMRES_CASES)
+def test_coarse_gmres_eo_parity(L, block, agg, prec, S, n_tv, n, m, tol):
+    """The even-odd preconditioned coarse solve (GMRES on the even-site Schur complement of
+    D_c, then the odd sites) and the self-block inverses against the oracle."""
+    need_gpu()
+    announce("coarse gmres eo L=%s n_tv=%d n=%d m=%d tol=%g" % (L, n_tv, n, m, tol))
+    case, op, qn, qin = _setup(L, block, agg, prec, S, n_tv, D32)
+    Vc, nc = op.n_agg, 2 * n_tv
+    Dc = torch.zeros(Vc * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+    mrhs.coarse_op_build(op.handle, qn, D32, n_tv, Dc, None)
+    Dh = Dc.cpu().double().numpy().view(np.complex128).reshape(Vc, 9, nc, nc)
+    Dinv = torch.full((Vc * nc * nc * 2,), float("nan"), dtype=torch.float32, device="cuda")
+    st = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    mrhs.coarse_self_invert(op.handle, Dc, n_tv, Dinv, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    inv = Dinv.cpu().double().numpy().view(np.complex128).reshape(Vc, nc, nc)
+    ref_inv = oracle.coarse_self_inverse(Dh)
+    assert np.max(np.linalg.norm((inv - ref_inv).reshape(Vc, -1), axis=1) /
+                  np.linalg.norm(ref_inv.reshape(Vc, -1), axis=1)) < 1e-5
+    rng = np.random.default_rng(335)
+    bc = rng.standard_normal((n, Vc, 2, n_tv)) + 1j * rng.standard_normal((n, Vc, 2, n_tv))
+    bc32 = (bc.real.astype(np.float32) + 1j * bc.imag.astype(np.float32)).astype(np.complex128)
+    bn = coarse_to_native(bc32, (n + 3) // 4 * 4)
+    un = op.coarse_empty(n_tv, n)
+    un.fill_(float("nan"))
+    res = torch.empty(n, dtype=torch.float64, device="cuda")
+    its = torch.empty(n, dtype=torch.int32, device="cuda")
+    ws = torch.empty(mrhs.mrhs_coarse_solve_eo_workspace_bytes(op.handle, n_tv, n, m), dtype=torch.uint8, device="cuda")
+    mrhs.coarse_solve_eo_mrhs(op.handle, Dc, Dinv, n_tv, bn, un, n, m, tol, ws, res, its)
+    got = coarse_from_native(un, Vc, n_tv, n)
+    ref, rref, iref = oracle.coarse_gmres_eo(L, agg, Dh, bc32, m, tol)
+    assert per_rhs_rel(got, ref) < 1e-5
+    assert np.array_equal(its.cpu().numpy(), iref)
+    r = res.cpu().numpy()
+    assert np.all(np.abs(r - rref) <= 1e-3 * rref + 1e-6)
+    if tol > 0:
+        assert np.all(r <= tol)
+    op.close()
+
+
+def test_coarse_eo_errors():
+    """an odd coarse extent is rejected; a singular self block is reported by site"""
+    need_gpu()
+    announce("coarse eo errors")
+    case, op, qn, qin = _setup([8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 4, D32)  # coarse extent 1 in z
+    Vc, nc, n = op.n_agg, 8, 2
+    Dc = torch.zeros(Vc * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+    mrhs.coarse_op_build(op.handle, qn, D32, 4, Dc, None)
+    Dinv = torch.empty(Vc * nc * nc * 2, dtype=torch.float32, device="cuda")
+    bn, un = op.coarse_empty(4, n), op.coarse_empty(4, n)
+    ws = torch.empty(mrhs.mrhs_coarse_solve_eo_workspace_bytes(op.handle, 4, n, 2), dtype=torch.uint8, device="cuda")
+    with pytest.raises(mrhs.MrhsError) as ei:
+        mrhs.coarse_solve_eo_mrhs(op.handle, Dc, Dinv, 4, bn, un, n, 2, 0.0, ws)
+    assert ei.value.code == mrhs.MRHS_EUNSUPPORTED
+    Dc.view(Vc, 9, -1)[3, 0] = 0.0  # site 3: zero self block
+    st = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    mrhs.coarse_self_invert(op.handle, Dc, 4, Dinv, st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 4
+    assert torch.all(Dinv.view(Vc, -1)[3] == 0)
+    op.close()
+
+
 @pytest.mark.parametrize("prec,qdt", [(F32, D32), (F64, D32), (F32, D16)])
 def test_setup_refine_parity(prec, qdt):
     """One refinement pass over all test vectors (Alg. 2, N_b = n_tv) against the oracle's
