@@ -23,6 +23,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
 
 constexpr int TTHR = 256;  // 4 wavefronts
+constexpr int PSPLIT = 4;  // workgroups per aggregate half in the prolongation
 constexpr int TNW = TTHR / 64;
 
 template <typename T> __device__ inline float to_f32(T v) { return (float)v; }
@@ -159,8 +160,9 @@ __global__ void __launch_bounds__(TTHR) k_restrict(TransArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
-// prolongation: one workgroup per (aggregate i, half h).  (y_c)^h_i is staged in LDS; each
-// wavefront forms 16-row blocks of Q^h_i (y_c)^h_i, K = the test vectors.
+// prolongation: PSPLIT workgroups per (aggregate i, half h), each taking every PSPLIT-th
+// group of 16-row blocks (the output rows are independent).  (y_c)^h_i is staged in LDS;
+// each wavefront forms 16-row blocks of Q^h_i (y_c)^h_i, K = the test vectors.
 // ---------------------------------------------------------------------------------------
 template <typename Tq, typename Ty>
 __global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
         yoff[t] = kok[t] ? tcol_off(a.g, k) : 0;
     }
     const int rows = 6 * a.Va;
-    for (int b0 = 16 * wave; b0 < rows; b0 += 16 * TNW) {
+    for (int b0 = 16 * (wave + TNW * (int)blockIdx.y); b0 < rows; b0 += 16 * TNW * (int)gridDim.y) {
         const int ra = b0 + (lane & 15);  // A operand row
         const bool raok = ra < rows;
         const uint32_t roa = raok ? trow_off(sbase, h, cstr, ra) : 0;
@@ -399,7 +401,7 @@ template <typename Tq, typename Ty> int restrict_typed(const TransArgs &a, hipSt
 template <typename Tq, typename Ty> int prolong_typed(const TransArgs &a, hipStream_t st)
 {
     const size_t lds = sizeof(uint32_t) * a.Va + sizeof(float) * 2048;
-    hipLaunchKernelGGL((k_prolong<Tq, Ty>), dim3(2 * a.n_agg), dim3(TTHR), lds, st, a);
+    hipLaunchKernelGGL((k_prolong<Tq, Ty>), dim3(2 * a.n_agg, PSPLIT), dim3(TTHR), lds, st, a);
     return hip_check(hipGetLastError(), "k_prolong launch");
 }
 
