@@ -48,7 +48,7 @@ FP32_ISSUE_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4
 SAP_SOURCES = ["paper_1601_03184_amd/csrc/sap.hip", "paper_1601_03184_amd/csrc/stencil.h",
                "paper_1601_03184_amd/csrc/internal.h"]
 SAP_TRAFFIC = {"sources_sha1": "c9b58bbecf8b0bd911d292b613501feab0e227b6", "fetch_scale": 2.0, "write_scale": 1.0,
-               "kib": {1: (191552, 86129), 2: (187617, 65069), 4: (205398, 71680)}}
+               "kib": {1: (190998, 86481), 2: (187957, 64908), 4: (205072, 71680)}}
 
 
 def sap_traffic_bytes(tile):
