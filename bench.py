@@ -398,7 +398,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the path would shard by domain decomposition; "
+        print("bench.py measures one GPU only (the path would shard by domain decomposition; "
               "no multi-GPU run is implemented)", file=sys.stderr)
         sys.exit(2)
     assert torch.cuda.is_available(), "bench needs a GPU"

@@ -58,7 +58,7 @@ extern "C" {
 /* return codes */
 #define MRHS_OK 0
 #define MRHS_EINVAL (-1)      /* null pointer, aliasing, bad size or geometry */
-#define MRHS_EUNSUPPORTED (-2) /* a shape / precision combination this build does not handle */
+#define MRHS_EUNSUPPORTED (-2) /* a shape / precision combination the library does not handle */
 #define MRHS_EHIP (-3)        /* HIP runtime or launch error (text in mrhs_last_error) */
 #define MRHS_ERANK (-4)       /* rank-deficient aggregate in block_orthonormalize */
 #define MRHS_ERANGE (-5)      /* value outside the FP16 range in mrhs_pack */
