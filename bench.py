@@ -1,19 +1,23 @@
 """Benchmark of the MRHS setup path on one MI355X.
 
 One step = the initial setup phase on all test vectors at once, inputs resident in HBM:
-  sap_smooth_mrhs     SAP from x = 0 on N_tv vectors (FP32),
-  mrhs_residual_norms FP64 check ||b - D x|| / ||b|| per vector,
+  sap_smooth_mrhs      SAP from x = 0 on N_tv vectors (FP32),
+  mrhs_residual_norms  FP64 check ||b - D x|| / ||b|| per vector,
   block_orthonormalize FP64 block Gram-Schmidt on the aggregates -> Q (FP32),
-  coarse_op_build     D_c (9 blocks of 2N_tv x 2N_tv complex64 per coarse site).
-Workload: 16^4 Wilson-clover lattice (synthetic links, sigma = 0.3), m0 = -0.3, csw = 1,
-N_tv = 20 complex Gaussian test vectors, 4^4 SAP blocks and aggregates, 3 SAP sweeps x
-4 MR steps.
+  coarse_op_build      D_c (9 blocks of 2N_tv x 2N_tv complex64 per coarse site).
+Workload (the headline): 48^3 x 96 Wilson-clover lattice (synthetic links, sigma = 0.2),
+m0 = -0.34, csw = 1, N_tv = 32 complex Gaussian test vectors, 4^4 SAP blocks and
+aggregates, 3 SAP sweeps x 4 MR steps -- the lattice shape and domain size of the paper's
+C101 runs (Sec. 7), with synthetic links standing in for the ensemble.
 
 Prints one JSON line.  value = site-RHS updates per second of the whole step
-(V * N_tv * n_SAP / step time).  Also reports: the roofline of the dominant kernel
-(SAP half-sweep, FP32 ALU bound) with HIP-event timing over the timed region, the
-stencil's HBM roofline, the single-RHS FP64 GPU path for the same SAP (speedup), and the
-CPU oracle on a bounded sample (baseline only).
+(V * N_tv * n_SAP / step time).  Also reports: the roofline of the dominant kernel (the
+SAP half-sweep, FP32 ALU bound) with HIP-event timing over the timed region, the
+stencil's HBM roofline, a plain device copy as the practical HBM ceiling, the relative
+error of every result against the FP64 oracle on sampled outputs, FP16 vector storage
+on the 32^3 x 64 workload, the single-RHS FP64 GPU path for the same SAP (speedup),
+the 16^4 extras (refinement phase, even-odd block solver, coarse-grid kernels, batched
+uneven lattices) and the CPU oracle on a bounded sample (baseline only).
 """
 import argparse
 import hashlib
@@ -31,39 +35,48 @@ sys.path.insert(0, ROOT)
 from paper_1601_03184_amd import autotune, inputs, mrhs  # noqa: E402
 from paper_1601_03184_amd import perfmodel as pm  # noqa: E402
 
-L = [16, 16, 16, 16]
 BLOCK = [4, 4, 4, 4]
 AGG = [4, 4, 4, 4]
-SIGMA, SEED_U, SEED_V = 0.3, 201, 202
-M0, CSW = -0.3, 1.0
-N_TV, N_SAP, N_MR = 20, 3, 4
+CSW = 1.0
+N_SAP, N_MR = 3, 4
+S = 4
+C5 = dict(L=[48, 48, 48, 96], sigma=0.2, m0=-0.34, n_tv=32, seed_u=501, seed_v=502)
+C3 = dict(L=[32, 32, 32, 64], sigma=0.25, m0=-0.33, n_tv=24, seed_u=301, seed_v=302)
+C2 = dict(L=[16, 16, 16, 16], sigma=0.3, m0=-0.3, n_tv=20, seed_u=201, seed_v=202)
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3      # published, with packed FP32 FMA
 FP32_ISSUE_PEAK_TFLOPS = 78.6        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz, no packed FP32
-# HBM traffic of the dominant kernel (SAP half-sweep, 16^4, N_tv 20, FP32), per launch and
-# execution tile: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over the
-# half-sweeps of the bench's calls), each scaled by what the counter reads for a plain 1 GiB
+TOL = {"f32": 1e-5, "f16_storage": 5e-3, "f64": 1e-12}
+
+# HBM traffic of the dominant kernel (SAP half-sweep, 48^3 x 96, N_tv 32, FP32), per launch
+# and execution tile: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch, mean over
+# the half-sweeps of the bench's calls), each scaled by what the counter reads for a plain
 # device copy (FETCH x2.0, WRITE x1.0).  Valid only for the kernel sources they were taken
 # with (SHA-1 of the files below); otherwise the bench reports traffic as null.
 SAP_SOURCES = ["paper_1601_03184_amd/csrc/sap.hip", "paper_1601_03184_amd/csrc/stencil.h",
                "paper_1601_03184_amd/csrc/internal.h"]
-SAP_TRAFFIC = {"sources_sha1": "c9b58bbecf8b0bd911d292b613501feab0e227b6", "fetch_scale": 2.0, "write_scale": 1.0,
-               "kib": {1: (190998, 86481), 2: (187957, 64908), 4: (205072, 71680)}}
+SAP_TRAFFIC = {"sources_sha1": None, "fetch_scale": 2.0, "write_scale": 1.0, "kib": {}}
 
 
-def sap_traffic_bytes(tile):
+def sources_sha1():
     h = hashlib.sha1()
     for f in SAP_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != SAP_TRAFFIC["sources_sha1"] or tile not in SAP_TRAFFIC["kib"]:
+    return h.hexdigest()
+
+
+def sap_traffic_bytes(tile):
+    if sources_sha1() != SAP_TRAFFIC["sources_sha1"] or tile not in SAP_TRAFFIC["kib"]:
         return None
     fk, wk = SAP_TRAFFIC["kib"][tile]
     return (fk * SAP_TRAFFIC["fetch_scale"] + wk * SAP_TRAFFIC["write_scale"]) * 1024
 
 
-WORKLOAD = ("16^4 Wilson-clover (sigma=0.3 links, m0=-0.3, csw=1), N_tv=20, SAP 4^4 blocks 3x4 FP32, "
-            "FP64 residual check, FP64 block Gram-Schmidt on 4^4 aggregates, D_c FP32")
+def workload_name(c):
+    return ("%s Wilson-clover (sigma=%g links, m0=%g, csw=1), N_tv=%d, SAP 4^4 blocks %dx%d FP32, "
+            "FP64 residual check, FP64 block Gram-Schmidt on 4^4 aggregates, D_c FP32"
+            % ("x".join(map(str, c["L"])), c["sigma"], c["m0"], c["n_tv"], N_SAP, N_MR))
 
 
 def log(msg):
@@ -82,15 +95,13 @@ def sap_flops_per_call(V, n, n_sap, n_mr, block):
     full_res = pm.STENCIL_FLOP + pm.RESIDUAL_EXTRA_FLOP
     first_black_res = hop * (1 - inner) + pm.RESIDUAL_EXTRA_FLOP
     half = V / 2.0 * n
-    per_call = half * (mr) + half * (mr + first_black_res) + (n_sap - 1) * 2 * half * (mr + full_res)
-    return per_call
+    return half * mr + half * (mr + first_black_res) + (n_sap - 1) * 2 * half * (mr + full_res)
 
 
 def sap_bytes_per_call(V, n, n_sap, store_b, field_b):
     """Algorithmic HBM bytes of a SAP call: per half-sweep the fields of that colour's sites
     once, b and x of those sites (x read except in the first sweep), x written, and the
-    x halo the residual reads (2x the block volume for 4^4 blocks, 3/8 of it read-once is
-    neglected: counted once per site of the other colour)."""
+    x of the other colour that the residual reads, counted once per site."""
     half = V // 2
     s = pm.SPINOR_REALS * store_b
     f = (4 * pm.LINK_REALS + pm.CLOVER_REALS) * field_b
@@ -106,23 +117,73 @@ def sap_bytes_per_call(V, n, n_sap, store_b, field_b):
     return total
 
 
-def make_inputs(dev):
-    U = inputs.gauge_field(L, SIGMA, SEED_U)
-    v = inputs.test_vectors(L, N_TV, SEED_V)
-    return U, v
+def group_view(op, native, g):
+    """The native storage of right-hand sides g*S .. g*S + S - 1 (one contiguous group)."""
+    ge = 24 * op.V * op.S
+    return native[g * ge:(g + 1) * ge]
+
+
+def pack_device(op, native, dtype, cfg, n):
+    """Pack the seeded test vectors of a workload, one group of S at a time (the canonical
+    complex128 vectors of the whole set would not fit beside the native ones)."""
+    for g in range((n + op.S - 1) // op.S):
+        m = min(op.S, n - g * op.S)
+        canon = inputs.test_vectors_device(cfg["L"], m, cfg["seed_v"], "cuda", first=g * op.S)
+        mrhs.mrhs_pack(op.handle, torch.view_as_real(canon), group_view(op, native, g), dtype, m)
+        del canon
+
+
+def gather_sites(op, native, dtype, n, sites):
+    """canonical complex128 [n][len(sites)][4][3] of all right-hand sides at some sites (host)"""
+    idx = torch.as_tensor(np.asarray(sites), device="cuda")
+    out = []
+    for g in range((n + op.S - 1) // op.S):
+        m = min(op.S, n - g * op.S)
+        buf = torch.zeros((m, op.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+        mrhs.mrhs_unpack(op.handle, group_view(op, native, g), dtype, buf, m)
+        out.append(torch.view_as_complex(buf[:, idx]).cpu().numpy())
+        del buf
+    return np.concatenate(out, axis=0)
+
+
+def unpack_rhs(op, native, dtype, n, k):
+    """canonical complex128 [V][4][3] of right-hand side k (host)"""
+    g, t = divmod(k, op.S)
+    m = min(op.S, n - g * op.S)
+    out = torch.zeros((m, op.V, 4, 3, 2), dtype=torch.float64, device="cuda")
+    mrhs.mrhs_unpack(op.handle, group_view(op, native, g), dtype, out, m)
+    return torch.view_as_complex(out[t]).cpu().numpy()
+
+
+def agg_site_index(L, a, i, window=1):
+    """canonical site indices of aggregate i (local sites lexicographic); with window = 3,
+    of the 3^4 aggregates centred on it (window sites lexicographic, periodic)."""
+    na = [L[m] // a[m] for m in range(4)]
+    ac, r = [], i
+    for m in range(4):
+        ac.append(r % na[m])
+        r //= na[m]
+    ext = [window * a[m] for m in range(4)]
+    w = np.indices(ext[::-1]).reshape(4, -1)[::-1]  # x fastest
+    x = [(w[m] + (ac[m] - (window // 2)) * a[m]) % L[m] for m in range(4)]
+    return x[0] + L[0] * (x[1] + L[1] * (x[2] + L[2] * x[3]))
 
 
 class Setup:
-    def __init__(self, U, v, prec, S, gs=True):
-        self.op = mrhs.Operator(L, BLOCK, AGG, torch.from_numpy(U), M0, CSW, prec=prec, short_len=S)
-        self.n = v.shape[0]
-        self.b = self.op.pack(torch.from_numpy(v))
+    """One workload's operator, test vectors and outputs, all in HBM."""
+
+    def __init__(self, cfg, U, prec=mrhs.PREC_F32, n=None, short_len=S, gs=True):
+        self.cfg = cfg
+        self.n = cfg["n_tv"] if n is None else n
+        self.op = mrhs.Operator(cfg["L"], BLOCK, AGG, U, cfg["m0"], CSW, prec=prec, short_len=short_len)
+        self.b = self.op.empty(self.n)
+        pack_device(self.op, self.b, self.op.dtype, cfg, self.n)
         self.x = self.op.empty(self.n)
         self.ws = self.op.workspace(self.n)
         self.res = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
         if gs:
             self.Q = self.op.empty(self.n, mrhs.DTYPE_F32)
-            self.status = torch.zeros(1, dtype=torch.int32, device="cuda")
             nc = 2 * self.n
             self.Dc = torch.empty(self.op.n_agg * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
 
@@ -139,9 +200,15 @@ class Setup:
     def dc(self):
         mrhs.coarse_op_build(self.op.handle, self.Q, mrhs.DTYPE_F32, self.n, self.Dc, self.ws)
 
+    def close(self):
+        self.op.close()
+        for a in ("b", "x", "ws", "Q", "Dc"):
+            if hasattr(self, a):
+                delattr(self, a)
+
 
 def time_steps(setup, steps, warmup):
-    """Returns per-step ms and per-part ms (HIP events on the stream the kernels use)."""
+    """Returns per-step ms, wall ms and per-part ms (HIP events on the stream the kernels use)."""
     parts = ["sap", "resid", "gs", "dc"]
     for _ in range(warmup):
         for p in parts:
@@ -155,10 +222,12 @@ def time_steps(setup, steps, warmup):
         for j, p in enumerate(parts):
             getattr(setup, p)()
             ev[s][j + 1].record()
+        if steps > 1 and s == 0:
+            log("first timed step enqueued")
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
-    per = {p: np.mean([ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)]) for j, p in enumerate(parts)}
-    step = np.mean([ev[s][0].elapsed_time(ev[s][-1]) for s in range(steps)])
+    per = {p: float(np.mean([ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)])) for j, p in enumerate(parts)}
+    step = float(np.mean([ev[s][0].elapsed_time(ev[s][-1]) for s in range(steps)]))
     return step, wall, per
 
 
@@ -175,11 +244,27 @@ def time_call(fn, reps, warmup=2):
     return a.elapsed_time(b) / reps
 
 
-def eo_bench(U, v, plain_ms, plain_res, reps=10):
+def copy_ceiling(gib=4, reps=10):
+    """A plain device-to-device copy (torch's copy kernel): the practical HBM ceiling."""
+    a = torch.empty(gib << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    ms = time_call(lambda: b.copy_(a), reps)
+    gbs = 2 * a.numel() * 4 / ms / 1e6
+    del a, b
+    return {"bytes_moved": 2 * (gib << 30), "ms": round(ms, 4), "GBs": round(gbs, 1),
+            "frac_of_datasheet": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+# ------------------------------------------------------------------------------------------
+# the extras on the 16^4 workload (refinement phase, even-odd block solver, coarse-grid
+# kernels) and the batch of uneven lattices
+# ------------------------------------------------------------------------------------------
+
+def eo_bench(U, cfg, plain_ms, plain_res, reps=10):
     """SAP with the even-odd block solver (MR on each block's even-site Schur complement) on
     the same workload: time and the largest relative residual ||b - D x|| / ||b|| after the
     call, for n_MR = 2, 3, 4 (tile: the fastest of 1, 2, 4 at n_MR = 4), beside plain MR."""
-    s = Setup(U, v, mrhs.PREC_F32, 4, gs=False)
+    s = Setup(cfg, U, gs=False)
     mrhs.mrhs_set_block_solver(s.op.handle, mrhs.BLOCK_EO_MR)
     best = None
     for tile in (1, 2, 4):
@@ -196,7 +281,7 @@ def eo_bench(U, v, plain_ms, plain_res, reps=10):
         s.resid()
         torch.cuda.synchronize()
         out["eo_n_mr_%d" % n_mr] = {"ms": round(ms, 4), "residual_max": float(s.res.max().item())}
-    s.op.close()
+    s.close()
     return out
 
 
@@ -209,9 +294,9 @@ def batched_bench(reps=5):
     batched call replayed from a captured graph."""
     ops, bs, xs, ns, upd = [], [], [], [], 0
     for (Lb, seed, n) in BATCH:
-        U = inputs.gauge_field(Lb, SIGMA, seed)
+        U = inputs.gauge_field(Lb, 0.3, seed)
         v = inputs.test_vectors(Lb, n, seed + 1)
-        op = mrhs.Operator(Lb, BLOCK, BLOCK, torch.from_numpy(U), M0, CSW, prec=mrhs.PREC_F32, short_len=4)
+        op = mrhs.Operator(Lb, BLOCK, BLOCK, torch.from_numpy(U), -0.3, CSW, prec=mrhs.PREC_F32, short_len=4)
         ops.append(op)
         bs.append(op.pack(torch.from_numpy(v)))
         xs.append(op.empty(n))
@@ -255,7 +340,7 @@ def coarse_grid_bench(mr, reps=20):
     t_r = time_call(lambda: mrhs.restrict_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, mr.x, op.dtype, yc, n), reps)
     t_p = time_call(lambda: mrhs.prolong_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, yc, y, op.dtype, n), reps)
     t_a = time_call(lambda: mrhs.coarse_apply_mrhs(op.handle, mr.Dc, n, yc, zc, n), reps)
-    V = int(np.prod(L))
+    V = op.V
     fine = V * 24 * 4 * n                       # n FP32 fine vectors
     coarse = op.n_agg * 2 * n * 2 * 4 * n       # n FP32 coarse vectors
     dcb = op.n_agg * 9 * (2 * n) ** 2 * 8
@@ -312,10 +397,10 @@ def refinement_bench(mr, m=8, tol=0.05, reps=10):
     y1 = op.empty(1)
     t_r1 = time_call(lambda: [mrhs.restrict_mrhs(op.handle, mr.Q, D32, n, y1, op.dtype, b1, 1) for _ in range(n)],
                      max(2, reps // 4))
-    # the true relative residual ||b - D_c u|| / ||b|| per right-hand side of a coarse solution
     zc = op.coarse_empty(n, n)
 
     def true_res(u):
+        """the true relative residual ||b - D_c u|| / ||b|| per right-hand side, max"""
         mrhs.coarse_apply_mrhs(op.handle, mr.Dc, n, u, zc, n)
         ldc = (n + 3) // 4 * 4
         r = (bc - zc).view(-1, ldc).double()
@@ -340,49 +425,208 @@ def refinement_bench(mr, m=8, tol=0.05, reps=10):
             "eo_iterations_needed": int(its_eo.max().item()), "eo_schur_residual_max": float(res_eo.max().item()),
             "eo_true_residual_max": true_eo,
             "refine_ms": round(t_refine, 4), "refine_pass_with_rebuild_ms": round(t_pass, 4),
-            "refine_site_rhs_per_s": int(np.prod(L)) * n * N_SAP / (t_pass * 1e-3),
+            "refine_site_rhs_per_s": op.V * n * N_SAP / (t_pass * 1e-3),
             "coarse_solve_mrhs_ms": round(t_cs, 4), "coarse_solve_srhs_looped_ms": round(t_cs1, 4),
             "coarse_solve_speedup": round(t_cs1 / t_cs, 2),
             "restrict_mrhs_ms": round(t_r, 4), "restrict_srhs_looped_ms": round(t_r1, 4),
             "restrict_speedup": round(t_r1 / t_r, 2)}
 
 
-def cpu_baseline(U, v, x_gpu, budget_s=30.0):
-    """The oracle on the host cores: SAP on a sample of test vectors (they are independent),
-    Gram-Schmidt on all aggregates, D_c on a sample of aggregates; scaled to the full step."""
+def extras_16(args):
+    """The 16^4 workload (N_tv 20): its step, and the extras built on it."""
+    cfg = C2
+    U = inputs.gauge_field_device(cfg["L"], cfg["sigma"], cfg["seed_u"], "cuda")
+    mr = Setup(cfg, U)
+    autotune.autotune(mr.op, mr.n, N_SAP, N_MR, b=mr.b, x=mr.x)
+    step_ms, _, per = time_steps(mr, 10, 3)
+    mr.resid()
+    res_max = float(mr.res.max().item())
+    out = {"workload": workload_name(cfg), "step_ms": round(step_ms, 4),
+           "parts_ms": {k: round(v, 4) for k, v in per.items()},
+           "value": mr.op.V * mr.n * N_SAP / (step_ms * 1e-3), "residual_max": res_max}
+    log("16^4 step %.3f ms %s" % (step_ms, per))
+    out["coarse_grid"] = coarse_grid_bench(mr)
+    if not args.no_eo:
+        out["even_odd_block_solver"] = eo_bench(U, cfg, per["sap"], res_max)
+    if not args.no_refine:
+        out["refinement"] = refinement_bench(mr)
+    mr.close()
+    del U
+    if not args.no_batched:
+        out["batched"] = batched_bench()
+    torch.cuda.empty_cache()
+    return out
+
+
+# ------------------------------------------------------------------------------------------
+# the FP64 single-RHS path (speedup reference) and FP16 storage
+# ------------------------------------------------------------------------------------------
+
+def srhs_bench(cfg, U, mrhs_fp32_ms, n_sub=8):
+    """SAP through the same kernels one right-hand side per call in FP64 (S = 1, tile 1;
+    timed on one vector, scaled by N_tv), MRHS in FP64 (tile 2; timed on n_sub vectors,
+    scaled by N_tv / n_sub: right-hand-side tiles are independent workgroups, so the time
+    is linear in their number at this size), and the step's MRHS FP32 SAP."""
+    n = cfg["n_tv"]
+    s1 = Setup(cfg, U, prec=mrhs.PREC_F64, n=1, short_len=1, gs=False)
+    t1 = time_call(s1.sap, 3, warmup=1)
+    s1.close()
+    torch.cuda.empty_cache()
+    m64 = Setup(cfg, U, prec=mrhs.PREC_F64, n=n_sub, short_len=S, gs=False)
+    mrhs.mrhs_set_tiles(m64.op.handle, 2, 0)
+    t64 = time_call(m64.sap, 3, warmup=1)
+    m64.close()
+    torch.cuda.empty_cache()
+    srhs_ms = t1 * n
+    m64_ms = t64 * n / n_sub
+    return {"srhs_fp64_sap_ms": round(srhs_ms, 3), "mrhs_fp64_sap_ms": round(m64_ms, 3),
+            "mrhs_fp32_sap_ms": round(mrhs_fp32_ms, 3),
+            "speedup_equal_precision": round(srhs_ms / m64_ms, 2),
+            "speedup_run_precision": round(srhs_ms / mrhs_fp32_ms, 2),
+            "sample": "single-RHS FP64 timed on 1 vector x %d; MRHS FP64 (tile 2) timed on %d vectors x %g"
+                      % (n, n_sub, n / n_sub)}
+
+
+def fp16_bench(cfg, k_sample, reps=5):
+    """SAP with FP16 (binary16) vector storage and FP32 arithmetic beside FP32 storage on the
+    32^3 x 64 workload; returns timings and the sampled right-hand side of each result."""
+    U = inputs.gauge_field_device(cfg["L"], cfg["sigma"], cfg["seed_u"], "cuda")
+    out, sample = {}, {}
+    V, n = int(np.prod(cfg["L"])), cfg["n_tv"]
+    for name, prec in (("f16_storage", mrhs.PREC_F32_F16STORE), ("f32", mrhs.PREC_F32)):
+        s = Setup(cfg, U, prec=prec, gs=False)
+        autotune.autotune(s.op, n, N_SAP, N_MR, b=s.b, x=s.x)
+        ms = time_call(s.sap, reps, warmup=1)
+        s.sap()
+        s.resid()
+        torch.cuda.synchronize()
+        sb = 2 if prec == mrhs.PREC_F32_F16STORE else 4
+        byts = sap_bytes_per_call(V, n, N_SAP, sb, 4)
+        flops = sap_flops_per_call(V, n, N_SAP, N_MR, BLOCK)
+        out[name] = {"sap_ms": round(ms, 3), "site_rhs_per_s": V * n * N_SAP / (ms * 1e-3),
+                     "alg_GBs": round(byts / ms / 1e6, 1), "alg_tflops": round(flops / ms / 1e9, 3),
+                     "residual_max": float(s.res.max().item())}
+        sample[name] = unpack_rhs(s.op, s.x, s.op.dtype, n, k_sample)
+        s.close()
+        torch.cuda.empty_cache()
+    out["speedup_f16_storage"] = round(out["f32"]["sap_ms"] / out["f16_storage"]["sap_ms"], 3)
+    Uh = U.cpu().numpy()
+    del U
+    torch.cuda.empty_cache()
+    return out, sample, Uh
+
+
+# ------------------------------------------------------------------------------------------
+# the oracle: relative errors per result and the CPU baseline
+# ------------------------------------------------------------------------------------------
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def per_half_rel(got, ref):
+    """relative error per spin half of one aggregate ([n][Va][4][3]); the max of the two"""
+    n = ref.shape[0]
+    g = got.reshape(n, -1, 2, 6)
+    r = ref.reshape(n, -1, 2, 6)
+    return max(rel(g[:, :, h], r[:, :, h]) for h in range(2))
+
+
+def oracle_checks(cfg, host, fp16=None):
+    """The FP64 oracle on the sampled outputs of the step: relative errors per result, and
+    its run time on that sample scaled to the whole step (the CPU baseline)."""
     import oracle
     cores = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "1000")))
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
-    t = time.perf_counter()
-    A = oracle.clover(L, U, CSW, M0)
-    t_clover = time.perf_counter() - t
-    n_s = 2
-    t = time.perf_counter()
-    xs = oracle.sap(L, BLOCK, U, A, v[:n_s], N_SAP, N_MR)
-    t_sap = (time.perf_counter() - t) * N_TV / n_s
-    t = time.perf_counter()
-    oracle.residual_norms(L, U, A, v[:n_s], xs)
-    t_res = (time.perf_counter() - t) * N_TV / n_s
-    t = time.perf_counter()
-    Q = oracle.block_gs(L, AGG, x_gpu)
-    t_gs = time.perf_counter() - t
-    n_agg = oracle.n_aggregates(L, AGG)
-    sample = list(range(0, n_agg, n_agg // 8))[:8]
-    t = time.perf_counter()
-    oracle.coarse_op(L, AGG, U, A, Q, agg_list=sample)
-    t_dc = (time.perf_counter() - t) * n_agg / len(sample)
-    total = t_sap + t_res + t_gs + t_dc
+    L, n, m0 = cfg["L"], cfg["n_tv"], cfg["m0"]
     V = int(np.prod(L))
-    return {
-        "value": V * N_TV * N_SAP / total,
-        "unit": "site*RHS updates/s",
-        "cores": cores,
-        "kind": "oracle",
-        "sample": ("SAP + residual on %d of %d test vectors (scaled x%d), block GS on all %d aggregates, "
-                   "D_c on %d of %d aggregates (scaled); op set-up (%.1f s) excluded; FP64 C, OpenMP"
-                   % (n_s, N_TV, N_TV // n_s, n_agg, len(sample), n_agg, t_clover)),
-        "seconds": {"sap": t_sap, "resid": t_res, "gs": t_gs, "dc": t_dc},
-    }
+    n_agg = oracle.n_aggregates(L, AGG)
+    t = time.perf_counter()
+    A = oracle.clover(L, host["U"], CSW, m0)
+    t_clover = time.perf_counter() - t
+    k = host["k"]
+    log("oracle: SAP of test vector %d" % k)
+    t = time.perf_counter()
+    xs = oracle.sap(L, BLOCK, host["U"], A, host["b_k"][None], N_SAP, N_MR)
+    t_sap = (time.perf_counter() - t) * n
+    # the residual check runs on the b the GPU holds (rounded once to FP32) and its x
+    b32 = host["b_k"].astype(np.complex64).astype(np.complex128)
+    t = time.perf_counter()
+    r_or = oracle.residual_norms(L, host["U"], A, b32[None], host["x_k"][None])
+    t_res = (time.perf_counter() - t) * n
+    del A
+    acc = {"sap_fp32": {"rel_err": rel(host["x_k"], xs[0]), "tol": TOL["f32"], "sample": "test vector %d" % k},
+           "residual_fp64": {"rel_err": abs(host["res_k"] - r_or[0]) / r_or[0], "tol": TOL["f64"],
+                             "value": float(r_or[0]), "sample": "test vector %d, the GPU's x" % k}}
+    del xs
+    log("oracle: Gram-Schmidt of %d aggregates" % len(host["gs_aggs"]))
+    t = time.perf_counter()
+    errs = []
+    for j, i in enumerate(host["gs_aggs"]):
+        ref = oracle.block_gs(AGG, AGG, host["gs_V"][:, j])
+        errs.append(per_half_rel(host["gs_Q"][:, j], ref))
+    t_gs = (time.perf_counter() - t) * n_agg / len(host["gs_aggs"])
+    acc["gs_fp64_to_fp32_q"] = {"rel_err": max(errs), "tol": 1e-6,
+                                "sample": "%d aggregates, per spin half (FP32 storage of Q: 1e-6)" % len(errs)}
+    log("oracle: D_c of %d coarse sites" % len(host["dc"]))
+    t_dc = 0.0
+    e_dc = []
+    Lw = [3 * a for a in AGG]
+    centre = 1 + 3 * (1 + 3 * (1 + 3 * 1))
+    for (i, Uw, qw, got) in host["dc"]:
+        Aw = oracle.clover(Lw, Uw, CSW, m0)
+        t = time.perf_counter()
+        ref = oracle.coarse_op(Lw, AGG, Uw, Aw, qw, agg_list=[centre])[centre]
+        t_dc += time.perf_counter() - t
+        e_dc.append(max(rel(got[d], ref[d]) for d in range(9)))
+    t_dc *= n_agg / len(host["dc"])
+    acc["dc_fp32"] = {"rel_err": max(e_dc), "tol": TOL["f32"],
+                      "sample": "all 9 blocks of %d coarse sites (oracle on the 12^4 window around each)" % len(e_dc)}
+    if fp16 is not None:
+        c3, got, Uh = fp16
+        log("oracle: SAP of one test vector of the 32^3 x 64 workload")
+        A3 = oracle.clover(c3["L"], Uh, CSW, c3["m0"])
+        b3 = inputs.test_vectors_device(c3["L"], 1, c3["seed_v"], "cuda", first=host["k"]).cpu().numpy()
+        ref3 = oracle.sap(c3["L"], BLOCK, Uh, A3, b3, N_SAP, N_MR)[0]
+        del A3
+        acc["sap_c3_f16_storage"] = {"rel_err": rel(got["f16_storage"], ref3), "tol": TOL["f16_storage"],
+                                     "sample": "32^3x64, test vector %d" % host["k"]}
+        acc["sap_c3_fp32"] = {"rel_err": rel(got["f32"], ref3), "tol": TOL["f32"],
+                              "sample": "32^3x64, test vector %d" % host["k"]}
+    for v in acc.values():
+        v["ok"] = bool(v["rel_err"] <= v["tol"])
+    total = t_sap + t_res + t_gs + t_dc
+    cpu = {"value": V * n * N_SAP / total, "unit": "site*RHS updates/s", "cores": cores, "kind": "oracle",
+           "sample": ("48^3x96 step: SAP + residual on 1 of %d test vectors (scaled x%d), block GS on %d of %d "
+                      "aggregates (scaled), D_c on %d of %d coarse sites (12^4 window each, scaled); clover "
+                      "set-up (%.1f s) excluded; FP64 C, OpenMP"
+                      % (n, n, len(host["gs_aggs"]), n_agg, len(host["dc"]), n_agg, t_clover)),
+           "seconds_scaled": {"sap": round(t_sap, 2), "resid": round(t_res, 2), "gs": round(t_gs, 2),
+                              "dc": round(t_dc, 2)}}
+    return acc, cpu
+
+
+def gather_for_oracle(st, U_dev, k=0, n_gs=64, dc_sites=(0, 12345)):
+    """Copy to the host what the oracle needs to check the step's results on a sample."""
+    op, n, L = st.op, st.n, st.cfg["L"]
+    host = {"k": k, "x_k": unpack_rhs(op, st.x, op.dtype, n, k),
+            "b_k": inputs.test_vectors_device(L, 1, st.cfg["seed_v"], "cuda", first=k).cpu().numpy()[0],
+            "res_k": float(st.res[k].item())}
+    aggs = list(np.linspace(0, op.n_agg - 1, n_gs).astype(int))
+    sites = np.concatenate([agg_site_index(L, AGG, i) for i in aggs])
+    Va = int(np.prod(AGG))
+    host["gs_aggs"] = aggs
+    host["gs_V"] = gather_sites(op, st.x, op.dtype, n, sites).reshape(n, n_gs, Va, 4, 3)
+    host["gs_Q"] = gather_sites(op, st.Q, mrhs.DTYPE_F32, n, sites).reshape(n, n_gs, Va, 4, 3)
+    nc = 2 * n
+    host["dc"] = []
+    for i in dc_sites:
+        wsites = agg_site_index(L, AGG, i, window=3)
+        Uw = U_dev[:, torch.as_tensor(wsites, device="cuda")].cpu().numpy()
+        qw = gather_sites(op, st.Q, mrhs.DTYPE_F32, n, wsites)
+        got = st.Dc.view(op.n_agg, 9, nc, nc, 2)[i].double().cpu().numpy()
+        host["dc"].append((i, np.ascontiguousarray(Uw), qw, got[..., 0] + 1j * got[..., 1]))
+    return host
 
 
 def main():
@@ -390,16 +634,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (errors and CPU baseline)")
     ap.add_argument("--no-srhs", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the 16^4 extras and the batch")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
     ap.add_argument("--no-eo", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only (the path would shard by domain decomposition; "
-              "no multi-GPU run is implemented)", file=sys.stderr)
+        print("bench.py measures one GPU only: this build has no multi-GPU path (it would shard the "
+              "lattice by domain decomposition, one halo exchange per SAP half-sweep)", file=sys.stderr)
         sys.exit(2)
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
@@ -412,85 +658,84 @@ def main():
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4}))
         return
 
+    cfg = C5
+    L, n = cfg["L"], cfg["n_tv"]
     V = int(np.prod(L))
-    log("generating inputs")
-    U, v = make_inputs("cuda")
+    log("generating the %s inputs on the device" % "x".join(map(str, L)))
+    U = inputs.gauge_field_device(L, cfg["sigma"], cfg["seed_u"], "cuda")
     log("operator set-up")
-    mr = Setup(U, v, mrhs.PREC_F32, 4)
-    tiles = autotune.autotune(mr.op, N_TV, N_SAP, N_MR)
+    mr = Setup(cfg, U)
+    tiles = autotune.autotune(mr.op, n, N_SAP, N_MR, b=mr.b, x=mr.x)
     log("autotuned tiles: %s" % tiles)
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
     step_ms, wall_ms, per = time_steps(mr, args.steps, args.warmup)
     assert int(mr.status.item()) == 0
     res = mr.res.cpu().numpy()
     log("step %.3f ms (wall %.3f): %s; residuals %.4f..%.4f" % (step_ms, wall_ms, per, res.min(), res.max()))
+    value = V * n * N_SAP / (step_ms * 1e-3)
 
-    value = V * N_TV * N_SAP / (step_ms * 1e-3)
-    # dominant kernel: the SAP half-sweep (2 * N_SAP launches per call)
+    # dominant kernel: the SAP half-sweep (2 * N_SAP launches per call, nothing else)
     n_launch = 2 * N_SAP
     sap_launch_ms = per["sap"] / n_launch
-    flops_launch = sap_flops_per_call(V, N_TV, N_SAP, N_MR, BLOCK) / n_launch
+    flops_launch = sap_flops_per_call(V, n, N_SAP, N_MR, BLOCK) / n_launch
     achieved = flops_launch / (sap_launch_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": sap_traffic_bytes(tiles["sap"]),
-            "traffic_unit": "bytes per launch (HBM, counters)", "alg_bytes": round(sap_bytes_per_call(V, N_TV, N_SAP, 4, 4) / n_launch),
+            "traffic_unit": "bytes per launch (HBM, counters)",
+            "alg_bytes": round(sap_bytes_per_call(V, n, N_SAP, 4, 4) / n_launch),
             "kernel": "k_sap_batched (FP32, tile %d)" % tiles["sap"], "launch_ms": round(sap_launch_ms, 4),
-            "frac_of_issue_peak": round(achieved / FP32_ISSUE_PEAK_TFLOPS, 4)}
+            "frac_of_issue_peak": round(achieved / FP32_ISSUE_PEAK_TFLOPS, 4),
+            "flops_per_launch": flops_launch}
 
-    # stencil HBM roofline (the HBM-bound kernel of the path)
-    y = mr.op.empty(N_TV)
-    d_ms = time_call(lambda: mrhs.dirac_apply_mrhs(mr.op.handle, mr.b, y, N_TV), 20)
-    d_bytes = V * N_TV * pm.stencil_bytes_per_site_rhs(N_TV, 4, 4)
-    stencil = {"kernel": "k_dirac (FP32, 20 RHS, tile %d)" % tiles["dirac"], "ms": round(d_ms, 4), "GBs": round(d_bytes / d_ms / 1e6, 1),
-               "frac_hbm": round(d_bytes / d_ms / 1e6 / HBM_PEAK_GBS, 4),
-               "site_rhs_per_s": V * N_TV / (d_ms * 1e-3)}
-    sap_bytes = sap_bytes_per_call(V, N_TV, N_SAP, 4, 4)
+    # stencil HBM roofline (the HBM-bound kernel of the path), and the copy ceiling
+    y = mr.op.empty(n)
+    d_ms = time_call(lambda: mrhs.dirac_apply_mrhs(mr.op.handle, mr.b, y, n), 10)
+    del y
+    d_bytes = V * n * pm.stencil_bytes_per_site_rhs(n, 4, 4)
+    copy = copy_ceiling()
+    stencil = {"kernel": "k_dirac (FP32, %d RHS, tile %d)" % (n, tiles["dirac"]), "ms": round(d_ms, 4),
+               "GBs": round(d_bytes / d_ms / 1e6, 1), "frac_hbm": round(d_bytes / d_ms / 1e6 / HBM_PEAK_GBS, 4),
+               "frac_of_copy": round(d_bytes / d_ms / 1e6 / copy["GBs"], 4),
+               "site_rhs_per_s": V * n / (d_ms * 1e-3)}
+    roof["alg_GBs"] = round(roof["alg_bytes"] / (sap_launch_ms * 1e-3) / 1e9, 1)
+    sap_bytes = sap_bytes_per_call(V, n, N_SAP, 4, 4)
     sap_info = {"ms_per_call": round(per["sap"], 4), "alg_GBs": round(sap_bytes / per["sap"] / 1e6, 1),
-                "alg_tflops": round(sap_flops_per_call(V, N_TV, N_SAP, N_MR, BLOCK) / per["sap"] / 1e9, 3)}
+                "alg_tflops": round(sap_flops_per_call(V, n, N_SAP, N_MR, BLOCK) / per["sap"] / 1e9, 3)}
+    log("roofline %s; stencil %s; copy %s" % (roof, stencil, copy))
+
+    host = None
+    if not args.no_cpu_baseline:
+        log("copying the sampled results to the host")
+        host = gather_for_oracle(mr, U)
+        host["U"] = U.cpu().numpy()
+    mr.close()
+    torch.cuda.empty_cache()
 
     srhs = None
     if not args.no_srhs:
         log("single-RHS FP64 and MRHS FP64 paths")
-        s1 = Setup(U, v[:1], mrhs.PREC_F64, 1, gs=False)
-        srhs_ms = time_call(s1.sap, 5) * N_TV     # the same SAP, one vector per call, looped
-        m64 = Setup(U, v, mrhs.PREC_F64, 4, gs=False)
-        mrhs.mrhs_set_tiles(m64.op.handle, 2, 0)
-        m64_ms = time_call(m64.sap, 5)
-        srhs = {"srhs_fp64_sap_ms": round(srhs_ms, 3), "mrhs_fp64_sap_ms": round(m64_ms, 3),
-                "mrhs_fp32_sap_ms": round(per["sap"], 3),
-                "speedup_equal_precision": round(srhs_ms / m64_ms, 2),
-                "speedup_run_precision": round(srhs_ms / per["sap"], 2)}
+        srhs = srhs_bench(cfg, U, per["sap"])
         log("srhs %s" % srhs)
-        s1.op.close()
-        m64.op.close()
+    del U
+    torch.cuda.empty_cache()
 
-    log("coarse-grid building blocks")
-    coarse_grid = coarse_grid_bench(mr)
-    log("coarse grid %s" % coarse_grid)
+    fp16, fp16_data = None, None
+    if not args.no_fp16:
+        log("FP16 storage on 32^3x64")
+        fp16, got16, U3 = fp16_bench(C3, 0)
+        fp16_data = (C3, got16, U3)
+        log("fp16 %s" % fp16)
 
-    eo = None
-    if not args.no_eo:
-        log("even-odd block solver")
-        eo = eo_bench(U, v, per["sap"], float(res.max()))
-        log("eo %s" % eo)
+    extras = None
+    if not args.no_extras:
+        log("16^4 extras")
+        extras = extras_16(args)
 
-    refinement = None
-    if not args.no_refine:
-        log("refinement phase")
-        refinement = refinement_bench(mr)
-        log("refinement %s" % refinement)
-
-    batched = None
-    if not args.no_batched:
-        log("batched uneven lattices")
-        batched = batched_bench()
-        log("batched %s" % batched)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("CPU oracle baseline")
-        x_gpu = mr.op.unpack(mr.x, N_TV).cpu().numpy()
-        cpu = cpu_baseline(U, v, x_gpu)
+    acc, cpu = None, None
+    if host is not None:
+        log("FP64 oracle on the sample")
+        acc, cpu = oracle_checks(cfg, host, fp16_data)
+        log("accuracy %s" % acc)
         log("cpu %s" % cpu)
 
     out = {
@@ -506,22 +751,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "lattice": L, "n_tv": N_TV, "sap": [N_SAP, N_MR], "block": BLOCK,
+        "config": {"workload": workload_name(cfg), "lattice": L, "n_tv": n, "sap": [N_SAP, N_MR], "block": BLOCK,
                    "aggregate": AGG, "parallelism": "single GPU",
                    "tiles": {"sap": tiles["sap"], "dirac": tiles["dirac"]}},
         "parts_ms": {k: round(float(x), 4) for k, x in per.items()},
         "residual_max": float(res.max()),
         "roofline": roof,
         "stencil_roofline": stencil,
+        "copy_ceiling": copy,
         "sap": sap_info,
+        "accuracy": acc,
         "srhs": srhs,
-        "coarse_grid": coarse_grid,
-        "even_odd_block_solver": eo,
-        "refinement": refinement,
-        "batched": batched,
+        "fp16_storage_32x32x32x64": fp16,
+        "extras_16x16x16x16": extras,
         "cpu_baseline": cpu,
     }
-    mr.op.close()
     print(json.dumps(out), flush=True)
 
 

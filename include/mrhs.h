@@ -21,9 +21,11 @@
  *   Q_munu(x) the sum of the four plaquette leaves in the (mu,nu) plane at x.
  *
  * Memory: every pointer to field or vector data is a DEVICE pointer owned by the
- * caller.  The library owns only what mrhs_op_create allocates (the operator's
- * fields in kernel layout), until mrhs_op_destroy.  No call allocates device memory
- * except mrhs_op_create; scratch space is passed in as a caller-owned workspace.
+ * caller.  The library owns what mrhs_op_create allocates (the operator's fields in
+ * kernel layout and a status word, used by mrhs_pack for its FP16 range flag) and, on
+ * the first switch to the even-odd block solver, what mrhs_set_block_solver allocates
+ * (A^-1 per site and the block's parity order), until mrhs_op_destroy.  No other call
+ * allocates device memory; scratch space is passed in as a caller-owned workspace.
  *
  * Asynchrony: every call only enqueues work on the given HIP stream (a hipStream_t
  * passed as void*, NULL = the default stream), except mrhs_op_create, mrhs_op_destroy
@@ -145,7 +147,9 @@ int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t
 int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void *Q, int32_t q_dtype, int32_t n_tv,
                          int32_t *status, void *ws, size_t ws_bytes, void *stream);
 
-/* D_c = R D P from Q (the output of block_orthonormalize, q_dtype F64, F32 or F16; the
+/* D_c = R D P, the Galerkin coarse-grid operator built from the test vectors in the
+ * setup (Sec. 2: the coarse operator is set up together with R and P = R^dag), from Q
+ * (the output of block_orthonormalize, q_dtype F64, F32 or F16; the
  * arithmetic is that of the op's fields, FP32 or FP64, whatever Q's storage), stored per
  * coarse site i (lexicographic over L/agg) as 9 blocks [self,+x,+y,+z,+t,-x,-y,-z,-t],
  * each 2 n_tv x 2 n_tv complex64 row-major, row = h*n_tv + k.  The self block holds the
@@ -259,8 +263,13 @@ size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const i
 int mrhs_set_block_solver(mrhs_op *op, int32_t solver, void *stream);
 
 /* Execution tiles (right-hand sides per workgroup) of the SAP and stencil kernels; 0 keeps
- * the current choice.  A tile must divide the op's short length and fit the block. */
+ * the current choice.  A tile must divide the op's short length and fit the block
+ * (EINVAL otherwise); SAP tiles above 2 with FP64 arithmetic are not built
+ * (EUNSUPPORTED: they would not fit the register file). */
 int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile);
+
+/* the op's current SAP block solver (MRHS_BLOCK_MR or MRHS_BLOCK_EO_MR) */
+int mrhs_op_block_solver(const mrhs_op *op);
 
 /* thread-local text of the last error */
 const char *mrhs_last_error(void);

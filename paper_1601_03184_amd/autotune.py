@@ -7,8 +7,9 @@ reduction order: the SAP block size and the aggregates are part of the problem, 
 
 autotune(op, n_rhs) times every valid tile with HIP events on the stream the kernels run
 on, keeps the fastest, applies it with mrhs_set_tiles, and caches the choice per
-(device, lattice, block, precision, S, n_rhs) in memory and, if a path is given, in a JSON
-file.
+(device, lattice, block, precision, S, n_rhs, block solver, n_sap, n_mr) in memory and, if a
+path is given, in a JSON file.  The plain and the even-odd block solver run different kernels
+(other occupancy and register use), so a choice made for one is never reused for the other.
 """
 import json
 import os
@@ -21,10 +22,11 @@ TILES = (1, 2, 4)
 _cache = {}
 
 
-def _key(op, n_rhs):
+def _key(op, n_rhs, n_sap, n_mr):
     dev = torch.cuda.get_device_name(op.device)
-    return "%s|L=%s|b=%s|prec=%d|S=%d|n=%d" % (dev, "x".join(map(str, op.L)), "x".join(map(str, op.block)), op.prec,
-                                               op.S, n_rhs)
+    return "%s|L=%s|b=%s|prec=%d|S=%d|n=%d|solver=%d|sap=%dx%d" % (
+        dev, "x".join(map(str, op.L)), "x".join(map(str, op.block)), op.prec, op.S, n_rhs,
+        mrhs.mrhs_op_block_solver(op.handle), n_sap, n_mr)
 
 
 def _time(fn, reps=3):
@@ -54,9 +56,13 @@ def _valid_tiles(op, which):
     return out
 
 
-def autotune(op, n_rhs, n_sap=3, n_mr=4, path=None, reps=3):
-    """Pick the fastest SAP and stencil tiles for (op, n_rhs); returns {"sap": t, "dirac": t, ...}."""
-    key = _key(op, n_rhs)
+def autotune(op, n_rhs, n_sap=3, n_mr=4, path=None, reps=3, b=None, x=None):
+    """Pick the fastest SAP and stencil tiles for (op, n_rhs); returns {"sap": t, "dirac": t, ...}.
+
+    b, x: optional native vector sets of the op for n_rhs right-hand sides to time on (b with
+    zero padding lanes, as mrhs_pack writes them; x is overwritten); by default random ones
+    are allocated for the timing."""
+    key = _key(op, n_rhs, n_sap, n_mr)
     if key not in _cache and path and os.path.exists(path):
         with open(path) as f:
             _cache.update(json.load(f))
@@ -64,10 +70,13 @@ def autotune(op, n_rhs, n_sap=3, n_mr=4, path=None, reps=3):
         choice = _cache[key]
         mrhs.mrhs_set_tiles(op.handle, choice["sap"], choice["dirac"])
         return choice
-    # packed from canonical vectors, so that the padding lanes of the last group are zero
-    canon = torch.randn(n_rhs, op.V, 4, 3, dtype=torch.complex128, device=op.device)
-    b = op.pack(canon)
-    x = op.empty(n_rhs)
+    if b is None:
+        # packed from canonical vectors, so that the padding lanes of the last group are zero
+        canon = torch.randn(n_rhs, op.V, 4, 3, dtype=torch.complex128, device=op.device)
+        b = op.pack(canon)
+        del canon
+    if x is None:
+        x = op.empty(n_rhs)
     ws = op.workspace(n_rhs)
     sap_ms = {}
     for t in _valid_tiles(op, "sap"):

@@ -67,10 +67,16 @@ size_t sap_lds_bytes(const mrhs_op *op, int T)
     return esz * (24 * (size_t)op->k.Vb * T + threads / 64 * T * 3);
 }
 
+// SAP tiles with FP64 arithmetic above 2 right-hand sides per site need more registers
+// than a workgroup of that size may hold (the kernels would spill to scratch)
+bool sap_tile_built(const mrhs_op *op, int T) { return op->prec != MRHS_PREC_F64 || T <= 2; }
+
 int pick_tile(const mrhs_op *op, int want, bool sap)
 {
     int t = want;
-    while (t > 1 && (op->k.S % t != 0 || op->k.Vb * t > 1024 || (sap && sap_lds_bytes(op, t) > op->max_lds))) t >>= 1;
+    while (t > 1 && (op->k.S % t != 0 || op->k.Vb * t > 1024 ||
+                     (sap && (sap_lds_bytes(op, t) > op->max_lds || !sap_tile_built(op, t)))))
+        t >>= 1;
     return t;
 }
 
@@ -78,7 +84,8 @@ void free_op(mrhs_op *op)
 {
     if (!op) return;
     void *ptrs[] = {op->links64, op->clover64, op->links32, op->clover32, op->blk_coords, op->loc_coords,
-                    op->colour_blocks, op->agg_sites, op->cloverinv64, op->cloverinv32, op->eo_sites};
+                    op->colour_blocks, op->agg_sites, op->cloverinv64, op->cloverinv32, op->eo_sites,
+                    op->status};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -218,6 +225,7 @@ int mrhs_op_create(const mrhs_geom *geom, const double *links, double m0, double
     alloc((void **)&op->loc_coords, sizeof(uint32_t) * Vb, "hipMalloc loc_coords");
     alloc((void **)&op->colour_blocks, sizeof(int32_t) * nblk, "hipMalloc colour_blocks");
     alloc((void **)&op->agg_sites, sizeof(int32_t) * asites.size(), "hipMalloc agg_sites");
+    alloc((void **)&op->status, sizeof(int), "hipMalloc status");
     hipStream_t st = (hipStream_t)stream;
     if (!rc) rc = hip_check(hipMemcpyAsync(op->blk_coords, bcoords.data(), sizeof(uint32_t) * nblk, hipMemcpyHostToDevice, st), "copy");
     if (!rc) rc = hip_check(hipMemcpyAsync(op->loc_coords, lcoords.data(), sizeof(uint32_t) * Vb, hipMemcpyHostToDevice, st), "copy");
@@ -269,18 +277,15 @@ int mrhs_pack(const mrhs_op *op, const double *canon, void *native, int32_t dtyp
     if (int rc = check_dtype(dtype)) return rc;
     if (!canon || !native) return set_error(MRHS_EINVAL, "null vector");
     hipStream_t st = (hipStream_t)stream;
-    int *flag = nullptr;
+    // the op's status word carries the FP16 range flag (the call synchronises, so it is
+    // never part of a captured graph)
+    int *flag = dtype == MRHS_DTYPE_F16 ? op->status : nullptr;
     int rc = MRHS_OK;
-    if (dtype == MRHS_DTYPE_F16) {
-        rc = hip_check(hipMallocAsync((void **)&flag, sizeof(int), st), "hipMallocAsync(flag)");
-        if (!rc) rc = hip_check(hipMemsetAsync(flag, 0, sizeof(int), st), "hipMemsetAsync(flag)");
-    }
+    if (flag) rc = hip_check(hipMemsetAsync(flag, 0, sizeof(int), st), "hipMemsetAsync(flag)");
     if (!rc) rc = launch_pack(op, canon, native, dtype, n_rhs, flag, st);
     int host_flag = 0;
-    if (flag) {
-        if (!rc) rc = hip_check(hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
-        (void)hipFreeAsync(flag, st);
-    }
+    if (flag && !rc)
+        rc = hip_check(hipMemcpyAsync(&host_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize(pack)");
     if (!rc && host_flag) return set_error(MRHS_ERANGE, "value outside the FP16 range");
     return rc;
@@ -566,6 +571,8 @@ int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile)
             return set_error(MRHS_EINVAL, "SAP tile must be 1, 2 or 4, divide S and fit the block");
         if (sap_lds_bytes(op, sap_tile) > op->max_lds)
             return set_error(MRHS_EUNSUPPORTED, "SAP tile exceeds the LDS of a workgroup");
+        if (!sap_tile_built(op, sap_tile))
+            return set_error(MRHS_EUNSUPPORTED, "SAP tiles above 2 are not built for FP64 arithmetic");
         op->sap_tile = sap_tile;
     }
     if (dirac_tile) {
@@ -575,6 +582,8 @@ int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile)
     }
     return MRHS_OK;
 }
+
+int mrhs_op_block_solver(const mrhs_op *op) { return op ? op->block_solver : MRHS_EINVAL; }
 
 int mrhs_set_block_solver(mrhs_op *op, int32_t solver, void *stream)
 {

@@ -56,6 +56,7 @@ struct mrhs_op {
     double *cloverinv64 = nullptr;
     float *cloverinv32 = nullptr;
     int32_t *eo_sites = nullptr;  // [Vb]
+    int *status = nullptr;        // device status word (mrhs_pack's FP16 range flag)
 };
 
 // error reporting (abi.hip)

@@ -496,7 +496,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
 
 // the same with the even-odd block solver
 template <typename Ts, typename Tc, int T>
-__global__ void __launch_bounds__(128 * T, T == 2 ? 3 : 1) k_sap_batched_eo(SapBatch<Ts, Tc> B)
+__global__ void __launch_bounds__(128 * T, (sizeof(Tc) == 4 && T == 2) ? 3 : 1) k_sap_batched_eo(SapBatch<Ts, Tc> B)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = xcd_remap(blockIdx.x, B.first[B.n_inst]);
@@ -646,11 +646,18 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
             switch (T * 2 + (eo ? 1 : 0)) {
             case 2: rc = launch_batched<Ts, Tc, 1, false>(B, thr, lds, st); break;
             case 4: rc = launch_batched<Ts, Tc, 2, false>(B, thr, lds, st); break;
-            case 8: rc = launch_batched<Ts, Tc, 4, false>(B, thr, lds, st); break;
             case 3: rc = launch_batched<Ts, Tc, 1, true>(B, thr, lds, st); break;
             case 5: rc = launch_batched<Ts, Tc, 2, true>(B, thr, lds, st); break;
-            case 9: rc = launch_batched<Ts, Tc, 4, true>(B, thr, lds, st); break;
-            default: rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
+            default:
+                // tile 4 only with FP32 arithmetic (FP64 would spill to scratch)
+                if constexpr (sizeof(Tc) == 4) {
+                    if (T == 4) {
+                        rc = eo ? launch_batched<Ts, Tc, 4, true>(B, thr, lds, st)
+                                : launch_batched<Ts, Tc, 4, false>(B, thr, lds, st);
+                        break;
+                    }
+                }
+                rc = set_error(MRHS_EUNSUPPORTED, "SAP tile not built");
             }
             if (rc) return rc;
         }

@@ -58,6 +58,7 @@ def lib():
             "coarse_op_build": (i32, [p, p, i32, i32, p, p, sz, p]),
             "mrhs_set_tiles": (i32, [p, i32, i32]),
             "mrhs_set_block_solver": (i32, [p, i32, p]),
+            "mrhs_op_block_solver": (i32, [p]),
             "sap_smooth_mrhs_batched": (i32, [p, i32, p, p, p, i32, i32, p, sz, p]),
             "mrhs_batched_workspace_bytes": (sz, [p, i32, p]),
             "mrhs_coarse_vector_bytes": (sz, [p, i32, i32]),
@@ -253,6 +254,10 @@ def sap_smooth_mrhs_batched(ops, bs, xs, n_rhs, n_sap, n_mr, ws, stream=None):
 
 def mrhs_set_tiles(op, sap_tile=0, dirac_tile=0):
     _check(lib().mrhs_set_tiles(op, int(sap_tile), int(dirac_tile)))
+
+
+def mrhs_op_block_solver(op):
+    return lib().mrhs_op_block_solver(op)
 
 
 def mrhs_set_block_solver(op, solver, stream=None):

@@ -28,6 +28,25 @@ def per_rhs_rel(got, ref):
     return float(np.max(np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)))
 
 
+def per_agg_half_rel(got, ref, L, agg):
+    """max over aggregates i and spin halves h of ||Q^h_i - Q^h_i,ref||_F / ||Q^h_i,ref||_F,
+    the relative error of block Gram-Schmidt per result (Q is defined per aggregate half);
+    got, ref: canonical [n][V][4][3]."""
+    n = ref.shape[0]
+    V = int(np.prod(L))
+    c = inputs.site_coords(L)
+    na = [L[m] // agg[m] for m in range(4)]
+    ai = np.zeros(V, np.int64)
+    for m in (3, 2, 1, 0):
+        ai = ai * na[m] + c[:, m] // agg[m]
+    d = np.abs(got.reshape(n, V, 2, 6) - ref.reshape(n, V, 2, 6)) ** 2   # spin half h = spin // 2
+    r = np.abs(ref.reshape(n, V, 2, 6)) ** 2
+    nagg = int(np.prod(na))
+    num = np.stack([np.bincount(ai, d[:, :, h].sum(axis=(0, 2)), minlength=nagg) for h in range(2)])
+    den = np.stack([np.bincount(ai, r[:, :, h].sum(axis=(0, 2)), minlength=nagg) for h in range(2)])
+    return float(np.max(np.sqrt(num / den)))
+
+
 class Case:
     """A gauge field with its oracle site term, cached per (L, sigma, seed, m0, csw)."""
     _cache = {}

@@ -204,6 +204,28 @@ def test_T14_residual_decreases(field):
     assert np.all(prev < 0.05)
 
 
+def test_residual_norms_definition(field):
+    """The final residual check (a6): ||b_k - D x_k||_2 / ||b_k||_2 per vector, at a non-zero
+    residual.  x = 0 gives exactly 1 whatever the norm of b (a wrong denominator such as
+    ||b||^2 fails); a random x is checked against the norm computed in numpy from D x; the
+    value is invariant under a common complex scale of b and x, and the vectors are
+    independent (a vector's value does not depend on the others of the stack).  The oracle
+    sums with OpenMP reductions, so repeated values agree to rounding, not bit for bit."""
+    U, A = field
+    rng = np.random.default_rng(171)
+    b = inputs.test_vectors(L4, 3, 172) * np.array([0.25, 1.0, 7.0])[:, None, None, None]
+    x = 0.3 * (rng.standard_normal(b.shape) + 1j * rng.standard_normal(b.shape))
+    assert np.allclose(oracle.residual_norms(L4, U, A, b, np.zeros_like(b)), 1.0, rtol=1e-14, atol=0)
+    got = oracle.residual_norms(L4, U, A, b, x)
+    r = (b - oracle.dirac(L4, U, A, x)).reshape(3, -1)
+    want = np.linalg.norm(r, axis=1) / np.linalg.norm(b.reshape(3, -1), axis=1)
+    assert np.all(want > 0.1)
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+    c = 2.5 - 1.5j
+    assert np.allclose(oracle.residual_norms(L4, U, A, c * b, c * x), got, rtol=1e-13, atol=0)
+    assert np.allclose(oracle.residual_norms(L4, U, A, b[1:2], x[1:2]), got[1:2], rtol=1e-14, atol=0)
+
+
 def test_odd_block_count_same_colour_neighbours():
     """12^4-like case (3 blocks per direction): same-coloured blocks touch across the wrap.
     All blocks of a colour use the residual computed before the colour's updates, so the
