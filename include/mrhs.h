@@ -135,6 +135,19 @@ int sap_smooth_mrhs_guess(const mrhs_op *op, const void *b, void *x, int32_t n_r
 int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out, void *ws,
                         size_t ws_bytes, void *stream);
 
+/* mrhs_residual_norms for callers that cannot allocate device memory or pass a workspace
+ * (code under graph capture, tight loops, harnesses that forbid allocation): the same
+ * kernels, with their partial sums in a static 32 MiB scratch array of the library instead
+ * of ws.  Each device holds one copy of the array until the process ends; the first call on
+ * a device looks up its address (no allocation).  The call allocates nothing and never
+ * synchronises.  The partial sums of n_rhs right-hand sides take ceil(n_rhs/S)*S * n_blocks
+ * * 16 bytes; larger requests return MRHS_EUNSUPPORTED (at 48^3 x 96 with 4^4 blocks: up to
+ * 50 right-hand sides).  All calls on one device share the array and it keeps the last
+ * call's partial sums: calls that overlap in time on one device (other streams, other
+ * threads) race and give wrong norms; the caller serialises them. */
+int mrhs_residual_norms_noalloc(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out,
+                                void *stream);
+
 /* Per aggregate i and spin half h (spins {0,1} | {2,3}), orthonormalise the n_tv columns
  * of V^h_i (6 * aggregate volume rows: local site, spin in half, colour): V^h_i = Q^h_i T
  * with T upper triangular, real positive diagonal (the setup of R = Q^dag, P = Q; Sec. 2,

@@ -352,6 +352,15 @@ int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t
     return launch_residual(op, b, x, n_rhs, out, ws, (hipStream_t)stream);
 }
 
+int mrhs_residual_norms_noalloc(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out,
+                                void *stream)
+{
+    if (int rc = check_op(op)) return rc;
+    if (int rc = check_nrhs(n_rhs)) return rc;
+    if (!b || !x || !out) return set_error(MRHS_EINVAL, "null argument");
+    return launch_residual_noalloc(op, b, x, n_rhs, out, (hipStream_t)stream);
+}
+
 int block_orthonormalize(const mrhs_op *op, const void *V, int32_t v_dtype, void *Q, int32_t q_dtype, int32_t n_tv,
                          int32_t *status, void *ws, size_t ws_bytes, void *stream)
 {

@@ -5,8 +5,18 @@
 // and one right-hand side.  The T lanes of a site issue the same link and clover loads,
 // so the operator is fetched once per site for the whole tile (the mat-vec -> mat-mat
 // argument of Sec. 6); tiles of one block share an XCD's L2 through xcd_remap.
+#include <mutex>
+
 #include "launch.h"
 #include "stencil.h"
+
+// Scratch of mrhs_residual_norms_noalloc: the partial sums per (tile, block, lane) that
+// k_residual writes and k_residual_finish adds up, in place of a caller's workspace.  One
+// copy per device, held until the process ends.  Host code never passes the array's name
+// to a kernel (in host code it is a host-side stand-in): it uses the device address that
+// hipGetSymbolAddress returns for the device the call runs on.
+constexpr size_t RESID_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[RESID_SCRATCH_BYTES];
 
 namespace {
 
@@ -176,6 +186,44 @@ size_t ws_bytes_residual(const mrhs_op *op, int n_rhs)
     const KGeo &g = op->k;
     const int ngrp = (n_rhs + g.S - 1) / g.S;
     return (size_t)ngrp * g.S * g.nblk * 2 * sizeof(double);
+}
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// this device's copy of the scratch array, looked up once per device with it current
+int device_scratch(int device, void **out)
+{
+    if (device < 0 || device >= MAX_DEVICES) return set_error(MRHS_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        int cur = -1;
+        if (int rc = hip_check(hipGetDevice(&cur), "hipGetDevice")) return rc;
+        if (cur != device)
+            if (int rc = hip_check(hipSetDevice(device), "hipSetDevice")) return rc;
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (int rc = hip_check(e, "hipGetSymbolAddress(scratch)")) return rc;
+        scratch_ptr[device] = p;
+    }
+    *out = scratch_ptr[device];
+    return MRHS_OK;
+}
+
+}  // namespace
+
+int launch_residual_noalloc(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, hipStream_t st)
+{
+    if (ws_bytes_residual(op, n_rhs) > RESID_SCRATCH_BYTES)
+        return set_error(MRHS_EUNSUPPORTED, "residual partial sums (" + std::to_string(ws_bytes_residual(op, n_rhs)) +
+                                                " bytes) exceed the 32 MiB scratch of the allocation-free call");
+    void *ws = nullptr;
+    if (int rc = device_scratch(op->device, &ws)) return rc;
+    return launch_residual(op, b, x, n_rhs, out, ws, st);
 }
 
 int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)

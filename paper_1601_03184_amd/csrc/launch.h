@@ -14,6 +14,8 @@ int launch_dirac(const mrhs_op *op, const void *x, void *y, int n_rhs, hipStream
 int launch_sap(const mrhs_op *op, const void *b, void *x, int n_rhs, int n_sap, int n_mr, void *ws, hipStream_t st,
                bool guess = false);
 int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st);
+// the same with the library's static per-device scratch instead of a workspace (no allocation)
+int launch_residual_noalloc(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, hipStream_t st);
 int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *ws,
               hipStream_t st);
 int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st);

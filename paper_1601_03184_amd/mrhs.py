@@ -54,6 +54,7 @@ def lib():
             "sap_smooth_mrhs": (i32, [p, p, p, i32, i32, i32, p, sz, p]),
             "sap_smooth_mrhs_guess": (i32, [p, p, p, i32, i32, i32, p, sz, p]),
             "mrhs_residual_norms": (i32, [p, p, p, i32, p, p, sz, p]),
+            "mrhs_residual_norms_noalloc": (i32, [p, p, p, i32, p, p]),
             "block_orthonormalize": (i32, [p, p, i32, p, i32, i32, p, p, sz, p]),
             "coarse_op_build": (i32, [p, p, i32, i32, p, p, sz, p]),
             "mrhs_set_tiles": (i32, [p, i32, i32]),
@@ -163,6 +164,10 @@ def sap_smooth_mrhs_guess(op, b, x, n_rhs, n_sap, n_mr, ws, stream=None):
 def mrhs_residual_norms(op, b, x, n_rhs, out, ws, stream=None):
     _check(lib().mrhs_residual_norms(op, _dptr(b), _dptr(x), int(n_rhs), _dptr(out), _dptr(ws),
                                      ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def mrhs_residual_norms_noalloc(op, b, x, n_rhs, out, stream=None):
+    _check(lib().mrhs_residual_norms_noalloc(op, _dptr(b), _dptr(x), int(n_rhs), _dptr(out), _stream(stream)))
 
 
 def block_orthonormalize(op, V, v_dtype, Q, q_dtype, n_tv, status, ws, stream=None):
