@@ -641,6 +641,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
     ap.add_argument("--no-eo", action="store_true")
+    ap.add_argument("--tiles", type=str, default=None, help="SAP,stencil tiles instead of the autotuner (e.g. 4,4)")
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -665,8 +666,13 @@ def main():
     U = inputs.gauge_field_device(L, cfg["sigma"], cfg["seed_u"], "cuda")
     log("operator set-up")
     mr = Setup(cfg, U)
-    tiles = autotune.autotune(mr.op, n, N_SAP, N_MR, b=mr.b, x=mr.x)
-    log("autotuned tiles: %s" % tiles)
+    if args.tiles:
+        ts, td = (int(t) for t in args.tiles.split(","))
+        mrhs.mrhs_set_tiles(mr.op.handle, ts, td)
+        tiles = {"sap": ts, "dirac": td, "fixed": True}
+    else:
+        tiles = autotune.autotune(mr.op, n, N_SAP, N_MR, b=mr.b, x=mr.x)
+    log("tiles: %s" % tiles)
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
     step_ms, wall_ms, per = time_steps(mr, args.steps, args.warmup)
     assert int(mr.status.item()) == 0

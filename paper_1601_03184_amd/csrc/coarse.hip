@@ -28,40 +28,56 @@ constexpr int NTHR = 256;
 constexpr int NW = NTHR / 64;
 constexpr int CHS = 8;  // sites per LDS chunk
 constexpr int NQ = 4;   // workgroups sharing the self block of an aggregate
+constexpr int MAXVA = 256;
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
     int a[4], na[4], astr[4];
     int Va, n_agg, N;
+    int sshift;          // log2 of the short length S
+    long gsz;            // elements of one group of S right-hand sides
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
     float *Dc;  // [n_agg][9][2N][2N][2]
 };
 
-__device__ inline void agg_local(const int (&a)[4], int ls, int (&lc)[4])
+// A site the workgroup touches: native index (fields), offset of its first element within a
+// group of the native vector layout, and its local coordinates in its aggregate (8 bits each)
+struct SiteRef {
+    int ns;
+    uint32_t vo;
+    uint32_t lc;
+};
+
+template <typename Tq>
+__device__ inline SiteRef site_ref(const CoarseArgs<Tq> &a, int i, int ls)
 {
+    SiteRef r;
+    r.ns = a.agg_sites[(size_t)i * a.Va + ls];
+    const int blk = r.ns / a.g.Vb, off = r.ns - blk * a.g.Vb;
+    r.vo = (uint32_t)(blk * 24) * (uint32_t)(a.g.Vb * a.g.S) + (uint32_t)(off * a.g.S);
+    uint32_t p = 0;
+    int q = ls;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        lc[mu] = ls % a[mu];
-        ls /= a[mu];
+        p |= (uint32_t)(q % a.a[mu]) << (8 * mu);
+        q /= a.a[mu];
     }
+    r.lc = p;
+    return r;
 }
 
-// spinor of column (HP, k') of P at native site ns: q_k' masked to spin half HP (the half
-// is a template parameter so that the masked spinor stays in registers)
+// spin half HP of column k' of P at a site: q_k' masked to that half (the half is a template
+// parameter so that the masked spinor stays in registers); qk points at q_k's group and lane
 template <int HP, typename Tc, typename Tq>
-__device__ inline void load_pcol(const KGeo &g, const Tq *Q, int kp, int ns, Spinor<Tc> &s)
+__device__ inline void load_half(const Tq *__restrict__ qk, uint32_t vo, uint32_t cs, Spinor<Tc> &s)
 {
-    const int blk = ns / g.Vb, off = ns - blk * g.Vb;
-    const int grp = kp / g.S, t = kp - grp * g.S;
-    const size_t base = (((size_t)grp * g.nblk + blk) * 24) * g.Vb * g.S + (size_t)off * g.S + t;
-    const size_t cs = (size_t)g.Vb * g.S;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         if (c / 6 == HP) {
-            s.re[c] = load_as<Tc>(Q + base + (2 * c) * cs);
-            s.im[c] = load_as<Tc>(Q + base + (2 * c + 1) * cs);
+            s.re[c] = load_as<Tc>(qk + vo + (2 * c) * cs);
+            s.im[c] = load_as<Tc>(qk + vo + (2 * c + 1) * cs);
         } else {
             s.re[c] = s.im[c] = Tc(0);
         }
@@ -69,24 +85,25 @@ __device__ inline void load_pcol(const KGeo &g, const Tq *Q, int kp, int ns, Spi
 }
 
 template <int MU, int HP, typename Tc, typename Tq>
-__device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *links, int i, int ls, int ns, const int (&lc)[4],
-                                   int kp, Spinor<Tc> &w)
+__device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const SiteRef *tab,
+                                   const SiteRef &me, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
 {
-    if (lc[MU] + 1 < a.a[MU]) {
-        const int nn = a.agg_sites[(size_t)i * a.Va + ls + a.astr[MU]];
+    const int l = unpack_coord(me.lc, MU);
+    if (l + 1 < a.a[MU]) {
+        const SiteRef n = tab[ls + a.astr[MU]];
         Spinor<Tc> chi;
-        load_pcol<HP, Tc>(a.g, a.Q, kp, nn, chi);
+        load_half<HP, Tc>(qk, n.vo, cs, chi);
         Tc U[18];
-        load_link(links, a.g.V, MU, ns, U);
+        load_link(links, a.g.V, MU, me.ns, U);
         hop_accumulate<MU, -1, false>(U, chi, w);
     }
     hop_fence(w);
-    if (lc[MU] > 0) {
-        const int nn = a.agg_sites[(size_t)i * a.Va + ls - a.astr[MU]];
+    if (l > 0) {
+        const SiteRef n = tab[ls - a.astr[MU]];
         Spinor<Tc> chi;
-        load_pcol<HP, Tc>(a.g, a.Q, kp, nn, chi);
+        load_half<HP, Tc>(qk, n.vo, cs, chi);
         Tc U[18];
-        load_link(links, a.g.V, MU, nn, U);
+        load_link(links, a.g.V, MU, n.ns, U);
         hop_accumulate<MU, +1, true>(U, chi, w);
     }
     hop_fence(w);
@@ -99,57 +116,52 @@ __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu,
     return f % st + st * (a[mu] - 1) + st * a[mu] * (f / st);
 }
 
-// column (HP, k') of the self part at aggregate site ls (native ns): (A + inside hops) P_c
+// column (HP, k') of the self part at aggregate site ls: (A + hops that stay inside) P_c
 template <int HP, typename Tc, typename Tq>
-__device__ inline void self_column(const CoarseArgs<Tq> &a, const Tc *links, const Tc *clover, int i, int ls, int ns,
-                                   int kp, Spinor<Tc> &w)
+__device__ inline void self_column(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const Tc *__restrict__ clover,
+                                   const SiteRef *tab, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
 {
-    int lc[4];
-    agg_local(a.a, ls, lc);
+    const SiteRef me = tab[ls];
     Spinor<Tc> p;
-    load_pcol<HP, Tc>(a.g, a.Q, kp, ns, p);
+    load_half<HP, Tc>(qk, me.vo, cs, p);
     // the site term is block-diagonal in the spin halves: only half HP is non-zero
     spinor_zero(w);
     {
         Tc A[36];
-        load_clover_half<HP>(clover, a.g.V, ns, A);
+        load_clover_half<HP>(clover, a.g.V, me.ns, A);
         clover_half<HP>(A, p, w);
     }
     hop_fence(w);
-    inside_hops<0, HP>(a, links, i, ls, ns, lc, kp, w);
-    inside_hops<1, HP>(a, links, i, ls, ns, lc, kp, w);
-    inside_hops<2, HP>(a, links, i, ls, ns, lc, kp, w);
-    inside_hops<3, HP>(a, links, i, ls, ns, lc, kp, w);
+    inside_hops<0, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_hops<1, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_hops<2, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_hops<3, HP>(a, links, tab, me, ls, qk, cs, w);
 }
 
-// column (HP, k') of the +MU face part at face site ns: (1 - g_mu) W_mu P_c(x + mu)
+// column (HP, k') of the +MU face part at face site f: (1 - g_mu) W_mu P_c(x + mu), the
+// neighbour x + mu in aggregate i + mu
 template <int MU, int HP, typename Tc, typename Tq>
-__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *links, int ns, int kp, Spinor<Tc> &w)
+__device__ inline void face_column(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const SiteRef &me,
+                                   const SiteRef &nb, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
 {
-    const KGeo &g = a.g;
-    const int blk = ns / g.Vb, off = ns - blk * g.Vb;
-    int bc[4], lcb[4];
-    decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lcb);
-    const NbrSite n = nbr_fwd(g, MU, blk, off, bc, lcb);
     Spinor<Tc> chi;
-    load_pcol<HP, Tc>(g, a.Q, kp, n.blk * g.Vb + n.off, chi);
+    load_half<HP, Tc>(qk, nb.vo, cs, chi);
     Tc U[18];
-    load_link(links, g.V, MU, ns, U);
+    load_link(links, a.g.V, MU, me.ns, U);
     spinor_zero(w);
     hop_accumulate<MU, -1, false>(U, chi, w);
 }
 
-// column (HP, k') of stencil part d (0 self, 1 + mu the +mu face) at site ls / ns
 template <int HP, typename Tc, typename Tq>
-__device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *links, const Tc *clover, int d, int i, int ls,
-                                   int ns, int kp, Spinor<Tc> &w)
+__device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const Tc *__restrict__ clover,
+                                   int d, const SiteRef *tab, int sidx, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
 {
     switch (d) {
-    case 0: self_column<HP>(a, links, clover, i, ls, ns, kp, w); break;
-    case 1: face_column<0, HP>(a, links, ns, kp, w); break;
-    case 2: face_column<1, HP>(a, links, ns, kp, w); break;
-    case 3: face_column<2, HP>(a, links, ns, kp, w); break;
-    default: face_column<3, HP>(a, links, ns, kp, w); break;
+    case 0: self_column<HP>(a, links, clover, tab, ls, qk, cs, w); break;
+    case 1: face_column<0, HP>(a, links, tab[sidx], tab[MAXVA + sidx], qk, cs, w); break;
+    case 2: face_column<1, HP>(a, links, tab[sidx], tab[MAXVA + sidx], qk, cs, w); break;
+    case 3: face_column<2, HP>(a, links, tab[sidx], tab[MAXVA + sidx], qk, cs, w); break;
+    default: face_column<3, HP>(a, links, tab[sidx], tab[MAXVA + sidx], qk, cs, w); break;
     }
 }
 
@@ -161,6 +173,8 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *links, con
 // ceil(N/16) x ceil(2N/16)), the wavefronts take tiles round-robin, a K step is 4 of the
 // (site, component) rows, and complex = 4 real products.  Lane l supplies
 // A[l%16][l/16] = conj(q)[row][kk] and B[l/16][l%16] = w[kk][col], holds D[4(l/16)+r][l%16].
+// The sites the workgroup touches are looked up once into an LDS table (native index,
+// vector offset, local coordinates), so the per-item work has no integer division.
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
@@ -171,8 +185,9 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N, N2 = 2 * N;
-    float2 *Qs = reinterpret_cast<float2 *>(smem);  // [CHS][12][N]
-    float2 *Ws = Qs + CHS * 12 * N;                // [CHS][12][2N]
+    SiteRef *tab = reinterpret_cast<SiteRef *>(smem);  // [MAXVA] own sites, [MAXVA] face neighbours
+    float2 *Qs = reinterpret_cast<float2 *>(tab + 2 * MAXVA);  // [CHS][12][N]
+    float2 *Ws = Qs + CHS * 12 * N;                           // [CHS][12][2N]
     // blockIdx.y < NQ: quarter q of the self part (partial sum into a -mu slot, summed by
     // k_coarse_finish); NQ + mu: the +mu face block
     const int i = blockIdx.x, q = blockIdx.y;
@@ -187,40 +202,61 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) accr[m] = acci[m] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // site table: self -- every site of aggregate i by local index; face -- the face sites
+    // in face order and their +mu neighbours in aggregate i + mu
+    if (self) {
+        for (int ls = threadIdx.x; ls < a.Va; ls += blockDim.x) tab[ls] = site_ref(a, i, ls);
+    } else {
+        int c[4], r = i;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            c[m] = r % a.na[m];
+            r /= a.na[m];
+        }
+        c[mu] = (c[mu] + 1) % a.na[mu];
+        const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
+        for (int f = threadIdx.x; f < nsites; f += blockDim.x) {
+            const int ls = face_site(a.a, a.astr, mu, f);
+            tab[f] = site_ref(a, i, ls);
+            tab[MAXVA + f] = site_ref(a, j, ls - (a.a[mu] - 1) * a.astr[mu]);
+        }
+    }
+    // this thread's test vector k (fixed) and its slot among the rows it serves
+    const int kt = threadIdx.x % N, rows_per_pass = NTHR / N, prow = threadIdx.x / N;
+    const Tq *qk = a.Q + (size_t)(kt >> a.sshift) * a.gsz + (kt & ((1 << a.sshift) - 1));
+    const uint32_t cs = (uint32_t)(a.g.Vb * a.g.S);
+
     for (int s0 = 0; s0 < nsites; s0 += CHS) {
         __syncthreads();
-        for (int e = threadIdx.x; e < CHS * 12 * N; e += blockDim.x) {
-            const int sl = e / (12 * N), rem = e - sl * 12 * N, comp = rem / N, k = rem - comp * N;
-            const int sidx = s0 + sl;
-            float2 v = make_float2(0.f, 0.f);
-            if (sidx < nsites) {
-                const int ls = self ? sbeg + sidx : face_site(a.a, a.astr, mu, sidx);
-                const int ns = a.agg_sites[(size_t)i * a.Va + ls];
-                const int blk = ns / a.g.Vb, off = ns - blk * a.g.Vb;
-                const int grp = k / a.g.S, t = k - grp * a.g.S;
-                const size_t base = (((size_t)grp * a.g.nblk + blk) * 24) * a.g.Vb * a.g.S + (size_t)off * a.g.S + t;
-                const size_t cs = (size_t)a.g.Vb * a.g.S;
-                v = make_float2((float)a.Q[base + (2 * comp) * cs], (float)a.Q[base + (2 * comp + 1) * cs]);
+        // rows: conj(q_k) at (site, component), one (site, component) row per thread and pass
+        if (prow < rows_per_pass) {
+            for (int rw = prow; rw < CHS * 12; rw += rows_per_pass) {
+                const int sl = rw / 12, comp = rw - sl * 12, sidx = s0 + sl;
+                float2 v = make_float2(0.f, 0.f);
+                if (sidx < nsites) {
+                    const uint32_t vo = tab[self ? sbeg + sidx : sidx].vo;
+                    v = make_float2(load_as<float>(qk + vo + (2 * comp) * cs),
+                                    load_as<float>(qk + vo + (2 * comp + 1) * cs));
+                }
+                Qs[rw * N + kt] = v;
             }
-            Qs[e] = v;
-        }
-        // columns: thread e -> (h', site, k'), k' fastest, so that a wavefront mostly
-        // shares one spin half
-        for (int e = threadIdx.x; e < 2 * CHS * N; e += blockDim.x) {
-            const int hp = e / (CHS * N), rem = e - hp * CHS * N, sl = rem / N, kp = rem - sl * N;
-            const int sidx = s0 + sl;
-            Spinor<Tc> w;
-            if (sidx < nsites) {
-                const int ls = self ? sbeg + sidx : face_site(a.a, a.astr, mu, sidx);
-                const int ns = a.agg_sites[(size_t)i * a.Va + ls];
-                if (hp == 0) part_column<0>(a, links, clover, d, i, ls, ns, kp, w);
-                else part_column<1>(a, links, clover, d, i, ls, ns, kp, w);
-            } else {
-                spinor_zero(w);
-            }
-            const int c = hp * N + kp;
+            // columns: (h', site) pairs, k' = kt; h' outermost, so that a wavefront mostly
+            // shares one spin half
+            for (int pr = prow; pr < 2 * CHS; pr += rows_per_pass) {
+                const int hp = pr / CHS, sl = pr - hp * CHS, sidx = s0 + sl;
+                Spinor<Tc> w;
+                if (sidx < nsites) {
+                    const int ls = self ? sbeg + sidx : 0;
+                    if (hp == 0) part_column<0>(a, links, clover, d, tab, sidx, ls, qk, cs, w);
+                    else part_column<1>(a, links, clover, d, tab, sidx, ls, qk, cs, w);
+                } else {
+                    spinor_zero(w);
+                }
+                const int c = hp * N + kt;
 #pragma unroll
-            for (int comp = 0; comp < 12; ++comp) Ws[(sl * 12 + comp) * N2 + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
+                for (int comp = 0; comp < 12; ++comp)
+                    Ws[(sl * 12 + comp) * N2 + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -233,13 +269,13 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 #pragma unroll 1
             for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
                 const int kk = kk0 + (lane >> 4), sl = kk / 6, comp = 6 * h + kk % 6;
-                const float2 q = k < N ? Qs[(sl * 12 + comp) * N + k] : make_float2(0.f, 0.f);
+                const float2 qv = k < N ? Qs[(sl * 12 + comp) * N + k] : make_float2(0.f, 0.f);
                 const float2 w = c < N2 ? Ws[(sl * 12 + comp) * N2 + c] : make_float2(0.f, 0.f);
                 // conj(q) w
-                accr[m] = mfma32(q.x, w.x, accr[m]);
-                accr[m] = mfma32(q.y, w.y, accr[m]);
-                acci[m] = mfma32(q.x, w.y, acci[m]);
-                acci[m] = mfma32(-q.y, w.x, acci[m]);
+                accr[m] = mfma32(qv.x, w.x, accr[m]);
+                accr[m] = mfma32(qv.y, w.y, accr[m]);
+                acci[m] = mfma32(qv.x, w.y, acci[m]);
+                acci[m] = mfma32(-qv.y, w.x, acci[m]);
             }
         }
     }
@@ -312,6 +348,9 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.Va = op->Va;
     a.n_agg = op->n_agg;
     a.N = n_tv;
+    a.sshift = 0;
+    while ((1 << a.sshift) < op->k.S) ++a.sshift;
+    a.gsz = (long)op->k.nblk * 24 * op->k.Vb * op->k.S;
     a.agg_sites = op->agg_sites;
     a.blk_coords = op->blk_coords;
     a.loc_coords = op->loc_coords;
@@ -319,7 +358,8 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.Dc = (float *)Dc;
     if (!a.Q || !a.Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
-    const size_t lds = sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
+    if (op->Va > MAXVA) return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate volume above 256");
+    const size_t lds = sizeof(SiteRef) * 2 * MAXVA + sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
     hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, NQ + 4), dim3(NTHR), lds, st, a, links, clover);
     if (int rc = hip_check(hipGetLastError(), "k_coarse launch")) return rc;
     hipLaunchKernelGGL((k_coarse_finish<Tq>), dim3(op->n_agg), dim3(NTHR), 0, st, a);

@@ -39,23 +39,32 @@ __global__ void __launch_bounds__(256 * T) k_dirac(KGeo g, const Tc *__restrict_
     store_spinor(g, y, grp, blk, off, tt, out);
 }
 
-// Per (block, tile): partial sums of |b - D x|^2 and |b|^2 per right-hand side, FP64.
+// Per (block, tile of T right-hand sides): partial sums of |b - D x|^2 and |b|^2 per
+// right-hand side, FP64.  A workgroup of (up to 64 sites) x T lanes walks the block in
+// passes of 64 sites, so that a workgroup is small (256 threads at T = 4) while the FP64
+// stencil takes ~130 registers: three workgroups share a CU instead of one.  The T lanes of
+// a site share its FP64 field loads.
+constexpr int RES_SITES = 64;
+
 template <typename Ts, int T>
-__global__ void __launch_bounds__(256 * T) k_residual(KGeo g, const double *__restrict__ links,
-                                                      const double *__restrict__ clover,
-                                                      const uint32_t *__restrict__ blk_coords,
-                                                      const uint32_t *__restrict__ loc_coords, const Ts *__restrict__ b,
-                                                      const Ts *__restrict__ x, int ntiles, double *__restrict__ part)
+__global__ void __launch_bounds__(RES_SITES * T) k_residual(KGeo g, const double *__restrict__ links,
+                                                            const double *__restrict__ clover,
+                                                            const uint32_t *__restrict__ blk_coords,
+                                                            const uint32_t *__restrict__ loc_coords,
+                                                            const Ts *__restrict__ b, const Ts *__restrict__ x,
+                                                            int ntiles, double *__restrict__ part)
 {
-    __shared__ double red[16][T][2];
+    __shared__ double red[RES_SITES * T / 64][T][2];
     // tiles of one block on one XCD, consecutively: the block's FP64 fields and its
     // neighbours' spinors are fetched into that XCD's L2 once for all its tiles
     const int li = xcd_remap(blockIdx.x, g.nblk * ntiles);
     const int blk = li / ntiles, tile = li - blk * ntiles;
-    const int off = threadIdx.x / T, t = threadIdx.x % T;
-    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;  // T divides S: grp is uniform
+    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + threadIdx.x % T;  // T divides S: grp is uniform
+    const int nsite = g.Vb < RES_SITES ? g.Vb : RES_SITES;
     double num = 0, den = 0;
-    if (off < g.Vb) {
+#pragma unroll 1
+    for (int o = threadIdx.x / T; o < g.Vb; o += nsite) {
+        const int off = opaque_index(o);
         int bc[4], lc[4];
         decode_site(g, blk_coords, loc_coords, blk, off, bc, lc);
         Spinor<double> Dx, bb;
@@ -78,7 +87,7 @@ __global__ void __launch_bounds__(256 * T) k_residual(KGeo g, const double *__re
     __syncthreads();
     if (threadIdx.x < T) {
         double sn = 0, sd = 0;
-        const int nw = blockDim.x >> 6;
+        const int nw = (blockDim.x + 63) >> 6;
         for (int w = 0; w < nw; ++w) {
             sn += red[w][threadIdx.x][0];
             sd += red[w][threadIdx.x][1];
@@ -152,18 +161,20 @@ int residual_launch(const mrhs_op *op, const void *b, const void *x, int n_rhs, 
     const int ngrp = (n_rhs + g.S - 1) / g.S;
     const int ntiles = ngrp * (g.S / T);
     double *part = (double *)ws;
-    hipLaunchKernelGGL((k_residual<Ts, T>), dim3(g.nblk * ntiles), dim3(round64(g.Vb * T)), 0, st, g, op->links64,
+    const int nsite = g.Vb < RES_SITES ? g.Vb : RES_SITES;
+    hipLaunchKernelGGL((k_residual<Ts, T>), dim3(g.nblk * ntiles), dim3(round64(nsite * T)), 0, st, g, op->links64,
                        op->clover64, op->blk_coords, op->loc_coords, (const Ts *)b, (const Ts *)x, ntiles, part);
     if (int rc = hip_check(hipGetLastError(), "k_residual launch")) return rc;
     hipLaunchKernelGGL((k_residual_finish<T>), dim3(n_rhs), dim3(256), 0, st, part, g.nblk, n_rhs, out);
     return hip_check(hipGetLastError(), "k_residual_finish launch");
 }
 
-// two lanes per site (the FP64 stencil needs ~150 VGPRs, so four lanes would spill)
+// as many lanes per site as the short length allows (up to 4)
 template <typename Ts>
 int residual_dispatch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
 {
-    if (op->k.S % 2 == 0 && op->k.Vb * 2 <= 512) return residual_launch<Ts, 2>(op, b, x, n_rhs, out, ws, st);
+    if (op->k.S % 4 == 0) return residual_launch<Ts, 4>(op, b, x, n_rhs, out, ws, st);
+    if (op->k.S % 2 == 0) return residual_launch<Ts, 2>(op, b, x, n_rhs, out, ws, st);
     return residual_launch<Ts, 1>(op, b, x, n_rhs, out, ws, st);
 }
 

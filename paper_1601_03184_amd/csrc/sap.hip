@@ -65,39 +65,95 @@ __device__ inline void lds_store(typename LdsPair<Tc>::type *rho, int str, int i
     for (int c = 0; c < 12; ++c) rho[c * str + idx] = {s.re[c], s.im[c]};
 }
 
+// The links a block operator uses, staged in LDS once per workgroup (the "links in LDS"
+// variant, for the tile of four right-hand sides): U_mu(x) for the block's sites x whose
+// +mu neighbour is inside the block (local coordinate l_mu < b_mu - 1; every site when the
+// block spans the lattice in mu and keeps its wrap-around hop).  Per direction they form a
+// box of extents e_mu,nu = b_nu, except e_mu,mu = b_mu - 1, stored lexicographically after
+// the boxes of the lower directions, 18 reals per link.
+struct LinkBox {
+    int base[4];  // first link of direction mu
+    int s[4][4];  // lexicographic strides of direction mu's box
+    int n;        // links in all four boxes
+};
+
+__host__ __device__ inline LinkBox link_box(const KGeo &g)
+{
+    LinkBox lb;
+    int base = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        int st = 1;
+        for (int nu = 0; nu < 4; ++nu) {
+            lb.s[mu][nu] = st;
+            st *= (nu == mu && g.nb[mu] > 1) ? g.b[nu] - 1 : g.b[nu];
+        }
+        lb.base[mu] = base;
+        base += st;
+    }
+    lb.n = base;
+    return lb;
+}
+
+template <typename Tf, typename T> __device__ inline void lds_link(const Tf *ul, int idx, T (&U)[18])
+{
+    using V2 = typename Vec2<Tf>::type;
+    const V2 *p = reinterpret_cast<const V2 *>(ul + idx * 18);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const V2 v = p[c];
+        U[2 * c] = (T)v.x;
+        U[2 * c + 1] = (T)v.y;
+    }
+}
+
 // q += hops of D_j rho at site off (lane t), rho from LDS; hops leaving the block dropped.
 // ns is the site's native index (opaque to the compiler, so the link loads stay inside
-// the MR loop).
-template <int MU, typename Tc>
+// the MR loop).  With ul (links in LDS) the links come from there: cf is the site's index
+// in direction MU's box, sb the box's stride in MU.
+template <int MU, typename Tc, bool LL = false>
 __device__ inline void block_hops(const KGeo &g, const Tc *__restrict__ links, const typename LdsPair<Tc>::type *rho,
-                                  int T, int ns, int off, int t, const int (&lc)[4], Spinor<Tc> &q)
+                                  int T, int ns, int off, int t, uint32_t lcp, Spinor<Tc> &q,
+                                  const Tc *ul = nullptr, int cf = 0, int sb = 0)
 {
     const int str = g.Vb * T;
+    const int l = unpack_coord(lcp, MU);
     int noff = -1;
-    if (lc[MU] + 1 < g.b[MU]) noff = off + g.ostr[MU];
+    if (l + 1 < g.b[MU]) noff = off + g.ostr[MU];
     else if (g.nb[MU] == 1) noff = off - (g.b[MU] - 1) * g.ostr[MU];
     if (noff >= 0) {
         Spinor<Tc> chi;
         lds_load<Tc>(rho, str, noff * T + t, chi);
         Tc U[18];
-        load_link(links, g.V, MU, ns, U);
+        if constexpr (LL) lds_link(ul, cf, U);
+        else load_link(links, g.V, MU, ns, U);
         hop_accumulate<MU, -1, false>(U, chi, q);
     }
     hop_fence(q);
     noff = -1;
-    if (lc[MU] > 0) noff = off - g.ostr[MU];
-    else if (g.nb[MU] == 1) noff = off + (g.b[MU] - 1) * g.ostr[MU];
+    int cb = 0;
+    if (l > 0) {
+        noff = off - g.ostr[MU];
+        cb = cf - sb;
+    } else if (g.nb[MU] == 1) {
+        noff = off + (g.b[MU] - 1) * g.ostr[MU];
+        cb = cf + (g.b[MU] - 1) * sb;
+    }
     if (noff >= 0) {
         Spinor<Tc> chi;
         lds_load<Tc>(rho, str, noff * T + t, chi);
         Tc U[18];
-        load_link(links, g.V, MU, ns + (noff - off), U);
+        if constexpr (LL) lds_link(ul, cb, U);
+        else load_link(links, g.V, MU, ns + (noff - off), U);
         hop_accumulate<MU, +1, true>(U, chi, q);
     }
 }
 
-// One workgroup's share of a half-sweep: block blk, right-hand-side tile `tile`.
-template <typename Ts, typename Tc, int T>
+// words of LDS for the reduction scratch of a workgroup: [waves][T][3], rounded to 4
+__host__ __device__ inline int red_words(int threads, int T) { return ((threads / 64) * T * 3 + 3) / 4 * 4; }
+
+// One workgroup's share of a half-sweep: block blk, right-hand-side tile `tile`.  LL: the
+// block's links are staged in LDS (after rho and the reduction scratch) for the MR steps.
+template <typename Ts, typename Tc, int T, bool LL>
 __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, unsigned char *smem)
 {
     using P2 = typename LdsPair<Tc>::type;
@@ -105,6 +161,7 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     P2 *rho = reinterpret_cast<P2 *>(smem);
     const int str = g.Vb * T;
     Tc *red_s = reinterpret_cast<Tc *>(rho + 12 * str);  // [waves][T][3]
+    Tc *ul = red_s + red_words(blockDim.x, T);  // used only with LL
 
     const int off = threadIdx.x / T, t = threadIdx.x % T;
     const bool active = off < g.Vb;
@@ -112,6 +169,29 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     const int me = off * T + t;                                   // this lane's LDS slot
     int bc[4] = {0, 0, 0, 0}, lc[4] = {0, 0, 0, 0};
     if (active) decode_site(g, a.blk_coords, a.loc_coords, blk, off, bc, lc);
+    const uint32_t lcp = active ? a.loc_coords[off] : 0u;  // local coordinates, 8 bits each
+    // links in LDS: this site's index in each direction's box; the T lanes of a site copy
+    // its four forward links (lane t: directions t, t + T, ...)
+    int cf[4] = {0, 0, 0, 0}, sb[4] = {0, 0, 0, 0};
+    if (LL) {
+        const LinkBox lb = link_box(g);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            cf[mu] = lb.base[mu] + lc[0] * lb.s[mu][0] + lc[1] * lb.s[mu][1] + lc[2] * lb.s[mu][2] + lc[3] * lb.s[mu][3];
+            sb[mu] = lb.s[mu][mu];
+        }
+        if (active) {
+            using V2 = typename Vec2<Tc>::type;
+            for (int mu = t; mu < 4; mu += T) {
+                if (lc[mu] + 1 < g.b[mu] || g.nb[mu] == 1) {
+                    const V2 *src = reinterpret_cast<const V2 *>(a.links + ((size_t)(blk * g.Vb + off) * 4 + mu) * 18);
+                    V2 *dst = reinterpret_cast<V2 *>(ul + cf[mu] * 18);
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) dst[c] = src[c];
+                }
+            }
+        }
+    }
 
     // 1. residual on the block
     if (active) {
@@ -152,13 +232,14 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
                 clover_site(a.clover, g.V, ns, own, q);
             }
             hop_fence(q);
-            block_hops<0>(g, a.links, rho, T, ns, off, t, lc, q);
+            // (the LDS link indices are hidden like ns: the links are re-read in every step)
+            block_hops<0, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[0]) : 0, sb[0]);
             hop_fence(q);
-            block_hops<1>(g, a.links, rho, T, ns, off, t, lc, q);
+            block_hops<1, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[1]) : 0, sb[1]);
             hop_fence(q);
-            block_hops<2>(g, a.links, rho, T, ns, off, t, lc, q);
+            block_hops<2, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[2]) : 0, sb[2]);
             hop_fence(q);
-            block_hops<3>(g, a.links, rho, T, ns, off, t, lc, q);
+            block_hops<3, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[3]) : 0, sb[3]);
             hop_fence(q);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -234,7 +315,7 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
 // -H_eo A_oo^-1 H_oe rho to A_ee rho directly.
 template <typename Ts, typename Tc, int T>
 __device__ inline void eo_hops(const SapArgs<Ts, Tc> &a, const typename LdsPair<Tc>::type *rho, int ns, int off, int t,
-                               const int (&lc)[4], Spinor<Tc> &h)
+                               uint32_t lc, Spinor<Tc> &h)
 {
     const KGeo &g = a.g;
     block_hops<0>(g, a.links, rho, T, ns, off, t, lc, h);
@@ -316,11 +397,8 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
     const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + t;
     const int se = active ? a.eo_sites[u] : 0, so = active ? a.eo_sites[Ve + u] : 0;
     const int me = se * T + t, mo = so * T + t;
-    int bc[4] = {0, 0, 0, 0}, lce[4] = {0, 0, 0, 0}, lco[4] = {0, 0, 0, 0};
-    if (active) {
-        decode_site(g, a.blk_coords, a.loc_coords, blk, se, bc, lce);
-        decode_site(g, a.blk_coords, a.loc_coords, blk, so, bc, lco);
-    }
+    // local coordinates of the even and the odd site, 8 bits each
+    const uint32_t lce = active ? a.loc_coords[se] : 0u, lco = active ? a.loc_coords[so] : 0u;
 
     // 1. residual on the block (sites u and u + Ve in site order), to LDS
     if (active) {
@@ -481,7 +559,7 @@ template <typename Ts, typename Tc> struct SapBatch {
     int n_inst;
 };
 
-template <typename Ts, typename Tc, int T>
+template <typename Ts, typename Tc, int T, bool LL>
 __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -491,7 +569,7 @@ __global__ void __launch_bounds__(256 * T) k_sap_batched(SapBatch<Ts, Tc> B)
     const SapArgs<Ts, Tc> &a = B.inst[k];
     const int li = w - B.first[k];
     const int bi = li / a.ntiles, tile = li - bi * a.ntiles;
-    sap_block<Ts, Tc, T>(a, a.blocks[bi], tile, smem);
+    sap_block<Ts, Tc, T, LL>(a, a.blocks[bi], tile, smem);
 }
 
 // the same with the even-odd block solver
@@ -544,10 +622,10 @@ template <> const float *op_cloverinv<float>(const mrhs_op *op) { return op->clo
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
-template <typename Ts, typename Tc, int T, bool EO>
+template <typename Ts, typename Tc, int T, bool EO, bool LL = false>
 int launch_batched(const SapBatch<Ts, Tc> &B, int threads, size_t lds, hipStream_t st)
 {
-    const void *fn = EO ? (const void *)k_sap_batched_eo<Ts, Tc, T> : (const void *)k_sap_batched<Ts, Tc, T>;
+    const void *fn = EO ? (const void *)k_sap_batched_eo<Ts, Tc, T> : (const void *)k_sap_batched<Ts, Tc, T, LL>;
     static size_t done = 0;
     if (lds > 65536 && lds > done) {
         if (int rc = hip_check(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
@@ -559,7 +637,7 @@ int launch_batched(const SapBatch<Ts, Tc> &B, int threads, size_t lds, hipStream
         hipLaunchKernelGGL((k_sap_batched_eo<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
         return hip_check(hipGetLastError(), "k_sap_batched_eo launch");
     } else {
-        hipLaunchKernelGGL((k_sap_batched<Ts, Tc, T>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
+        hipLaunchKernelGGL((k_sap_batched<Ts, Tc, T, LL>), dim3(B.first[B.n_inst]), dim3(threads), lds, st, B);
         return hip_check(hipGetLastError(), "k_sap_batched launch");
     }
 }
@@ -580,8 +658,15 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
     }
     const int threads = round64(maxVb * T);
     const int eo_threads = round64(maxVb / 2 * T);  // even-odd: one even and one odd site per thread
-    const size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + (size_t)(threads / 64) * T * 3);
+    size_t lds = sizeof(Tc) * (24 * (size_t)maxVb * T + red_words(threads, T));
     if (maxVb * T > 1024 || lds > max_lds) return set_error(MRHS_EUNSUPPORTED, "batched SAP tile does not fit");
+    // the plain MR kernel at tile 4 with FP32 arithmetic stages the block's links in LDS when
+    // they fit beside rho
+    int max_links = 0;
+    for (int k = 0; k < n; ++k) max_links = std::max(max_links, link_box(ops[k]->k).n);
+    const size_t lds_ll = lds + sizeof(Tc) * 18 * (size_t)max_links;
+    const bool ll = !eo && sizeof(Tc) == 4 && T == 4 && lds_ll <= max_lds;
+    if (ll) lds = lds_ll;
     if (n_sap == 0) {
         if (guess) return MRHS_OK;  // no sweep: x keeps the starting guess
         for (int k = 0; k < n; ++k) {
@@ -653,6 +738,7 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
                 if constexpr (sizeof(Tc) == 4) {
                     if (T == 4) {
                         rc = eo ? launch_batched<Ts, Tc, 4, true>(B, thr, lds, st)
+                           : ll ? launch_batched<Ts, Tc, 4, false, true>(B, thr, lds, st)
                                 : launch_batched<Ts, Tc, 4, false>(B, thr, lds, st);
                         break;
                     }
