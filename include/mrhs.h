@@ -119,8 +119,11 @@ int dirac_apply_mrhs(const mrhs_op *op, const void *x, void *y, int32_t n_rhs, v
  * b - D x is formed on that colour's blocks, then every block j adds n_mr minimal-
  * residual steps on D_j = I_j^T D I_j (step length 0 when <q,q> = 0).  b, x: native
  * vectors of the op's element type, x != b; x is overwritten.  ws: workspace of at
- * least mrhs_workspace_bytes(op, n_rhs) bytes (used when a direction holds an odd
- * number of blocks). */
+ * least mrhs_workspace_bytes(op, n_rhs) bytes: with the plain MR block solver it carries
+ * sigma_j = b_j - D_j x_j (arithmetic type, one vector set) from one visit of a block to
+ * the next, so that a later residual is sigma_j minus the hops across the block's faces
+ * (the same residual up to rounding order); a snapshot of x when a direction holds an odd
+ * number of blocks. */
 int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
                     void *ws, size_t ws_bytes, void *stream);
 

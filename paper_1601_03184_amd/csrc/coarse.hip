@@ -9,14 +9,12 @@
 // The last line is exact: the -mu face hop of i is the adjoint of the +mu face hop of i-mu
 // conjugated by g5, and g5 acts on the coarse index as sigma3 = diag(1, -1) over halves.
 //
-// k_coarse      : per (aggregate i, block d in self,+x..+t), the sites of the block's set
-//                 (all sites for self, the +mu face for +mu) in chunks of CHS: the chunk's
-//                 rows conj(q_k) and its columns w_c = (stencil part d) P_c, computed from
-//                 Q on the vector units, go to LDS; the 2N x 2N product accumulates on the
-//                 matrix cores.  Nothing is written to memory but D_c.
-//                 The self block is split over NQ workgroups (quarters of the sites).
-// k_coarse_finish: the self block from the quarters, then the four -mu blocks by the
-//                 sigma3 relation
+// k_coarse: per (aggregate i, block d in self,+x..+t), the sites of the block's set (all
+//           sites for self, the +mu face for +mu) in chunks of CHS: the chunk's rows
+//           conj(q_k) and its columns w_c = (stencil part d) P_c, computed from Q on the
+//           vector units, go to LDS; the 2N x 2N product accumulates on the matrix cores.
+//           A +mu workgroup writes its block and, by the sigma3 relation, the -mu block of
+//           aggregate i + mu.  Nothing is written to memory but D_c.
 #include <algorithm>
 
 #include "launch.h"
@@ -24,11 +22,11 @@
 
 namespace {
 
-constexpr int NTHR = 256;
+constexpr int NTHR = 512;  // 8 wavefronts: one column item per thread and chunk at 32 vectors
 constexpr int NW = NTHR / 64;
 constexpr int CHS = 8;  // sites per LDS chunk
-constexpr int NQ = 4;   // workgroups sharing the self block of an aggregate
 constexpr int MAXVA = 256;
+constexpr int MAXFACE = 64;  // face sites of an aggregate whose neighbours the table holds
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
@@ -165,7 +163,7 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *__restrict
     }
 }
 
-// grid: (aggregate i, part: NQ quarters of self, then +mu).  A 2N x 2N block is a sum over the
+// grid: (aggregate i, part: self, then +mu).  A 2N x 2N block is a sum over the
 // block's sites and the 6 components of each spin half: rows (h, k) = conj(q_k) of half h,
 // columns c = (h', k') the stencil part d applied to P_c.  Both are formed a chunk of CHS
 // sites at a time in LDS (the columns by one thread per (h', site, k')); the
@@ -185,19 +183,21 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N, N2 = 2 * N;
-    SiteRef *tab = reinterpret_cast<SiteRef *>(smem);  // [MAXVA] own sites, [MAXVA] face neighbours
-    float2 *Qs = reinterpret_cast<float2 *>(tab + 2 * MAXVA);  // [CHS][12][N]
-    float2 *Ws = Qs + CHS * 12 * N;                           // [CHS][12][2N]
-    // blockIdx.y < NQ: quarter q of the self part (partial sum into a -mu slot, summed by
-    // k_coarse_finish); NQ + mu: the +mu face block
-    const int i = blockIdx.x, q = blockIdx.y;
-    const bool self = q < NQ;
-    const int mu = q - NQ, d = self ? 0 : 1 + mu;
-    const int sbeg = self ? q * a.Va / NQ : 0;
-    const int nsites = self ? (q + 1) * a.Va / NQ - sbeg : a.Va / a.a[mu];
+    // rows of Qs and Ws are padded by one pair, so that the four rows a matrix-core step
+    // reads fall on different LDS banks
+    const int QST = N + 1, WST = 2 * N + 1;
+    SiteRef *tab = reinterpret_cast<SiteRef *>(smem);  // [MAXVA] own sites, [MAXFACE] face neighbours
+    float2 *Qs = reinterpret_cast<float2 *>(tab + MAXVA + MAXFACE);  // [CHS][12][QST]
+    float2 *Ws = Qs + CHS * 12 * QST;                               // [CHS][12][WST]
+    // blockIdx.y = 0: the self block; 1 + mu: the +mu face block
+    const int i = blockIdx.x, d = blockIdx.y;
+    const bool self = d == 0;
+    const int mu = d - 1;
+    const int nsites = self ? a.Va : a.Va / a.a[mu];
+    int j = i;  // the aggregate across the +mu face
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int TR = (N + 15) / 16, TC = (N2 + 15) / 16, ntile = 2 * TR * TC;
-    constexpr int MAXT = 4;  // tiles per wavefront (N <= 32: at most 16 tiles, 4 wavefronts)
+    constexpr int MAXT = (16 + NW - 1) / NW;  // tiles per wavefront (N <= 32: at most 16 tiles)
     f4 accr[MAXT], acci[MAXT];
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) accr[m] = acci[m] = f4{0.f, 0.f, 0.f, 0.f};
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             r /= a.na[m];
         }
         c[mu] = (c[mu] + 1) % a.na[mu];
-        const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
+        j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
         for (int f = threadIdx.x; f < nsites; f += blockDim.x) {
             const int ls = face_site(a.a, a.astr, mu, f);
             tab[f] = site_ref(a, i, ls);
@@ -234,11 +234,11 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
                 const int sl = rw / 12, comp = rw - sl * 12, sidx = s0 + sl;
                 float2 v = make_float2(0.f, 0.f);
                 if (sidx < nsites) {
-                    const uint32_t vo = tab[self ? sbeg + sidx : sidx].vo;
+                    const uint32_t vo = tab[sidx].vo;
                     v = make_float2(load_as<float>(qk + vo + (2 * comp) * cs),
                                     load_as<float>(qk + vo + (2 * comp + 1) * cs));
                 }
-                Qs[rw * N + kt] = v;
+                Qs[rw * QST + kt] = v;
             }
             // columns: (h', site) pairs, k' = kt; h' outermost, so that a wavefront mostly
             // shares one spin half
@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
                 const int hp = pr / CHS, sl = pr - hp * CHS, sidx = s0 + sl;
                 Spinor<Tc> w;
                 if (sidx < nsites) {
-                    const int ls = self ? sbeg + sidx : 0;
+                    const int ls = self ? sidx : 0;
                     if (hp == 0) part_column<0>(a, links, clover, d, tab, sidx, ls, qk, cs, w);
                     else part_column<1>(a, links, clover, d, tab, sidx, ls, qk, cs, w);
                 } else {
@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
                 const int c = hp * N + kt;
 #pragma unroll
                 for (int comp = 0; comp < 12; ++comp)
-                    Ws[(sl * 12 + comp) * N2 + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
+                    Ws[(sl * 12 + comp) * WST + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
             }
         }
         __syncthreads();
@@ -269,8 +269,8 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 #pragma unroll 1
             for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
                 const int kk = kk0 + (lane >> 4), sl = kk / 6, comp = 6 * h + kk % 6;
-                const float2 qv = k < N ? Qs[(sl * 12 + comp) * N + k] : make_float2(0.f, 0.f);
-                const float2 w = c < N2 ? Ws[(sl * 12 + comp) * N2 + c] : make_float2(0.f, 0.f);
+                const float2 qv = k < N ? Qs[(sl * 12 + comp) * QST + k] : make_float2(0.f, 0.f);
+                const float2 w = c < N2 ? Ws[(sl * 12 + comp) * WST + c] : make_float2(0.f, 0.f);
                 // conj(q) w
                 accr[m] = mfma32(qv.x, w.x, accr[m]);
                 accr[m] = mfma32(qv.y, w.y, accr[m]);
@@ -279,7 +279,10 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             }
         }
     }
-    float *out = a.Dc + ((size_t)i * 9 + (self ? 5 + q : d)) * N2 * N2 * 2;
+    // D_c(i, i) or D_c(i, i + mu); for a face also D_c(i + mu, i) = sigma3 D_c(i, i + mu)^dag sigma3
+    // into the -mu slot of aggregate j = i + mu (each slot has exactly one writer)
+    float *out = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
+    float *bwd = a.Dc + ((size_t)j * 9 + 5 + mu) * N2 * N2 * 2;
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) {
         const int tile = wave + NW * m;
@@ -290,44 +293,17 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
         for (int r = 0; r < 4; ++r) {
             const int k = tr * 16 + 4 * (lane >> 4) + r;
             if (k < N && c < N2) {
-                const size_t e = (size_t)(h * N + k) * N2 + c;
+                const int row = h * N + k;
+                const size_t e = (size_t)row * N2 + c;
                 out[2 * e] = accr[m][r];
                 out[2 * e + 1] = acci[m][r];
+                if (!self) {
+                    const float sg = ((row < N) == (c < N)) ? 1.f : -1.f;
+                    const size_t t = (size_t)c * N2 + row;
+                    bwd[2 * t] = sg * accr[m][r];
+                    bwd[2 * t + 1] = -sg * acci[m][r];
+                }
             }
-        }
-    }
-}
-
-// per aggregate: the self block = the NQ partial sums (kept in the -mu slots), added in a
-// fixed order; then D_c(i, i - mu) = sigma3 D_c(i - mu, i)^dag sigma3 into those slots
-template <typename Tq> __global__ void k_coarse_finish(CoarseArgs<Tq> a)
-{
-    const int i = blockIdx.x;
-    const int N2 = 2 * a.N, nout = N2 * N2;
-    float *blocks = a.Dc + (size_t)i * 9 * nout * 2;
-    for (int e = threadIdx.x; e < 2 * nout; e += blockDim.x) {
-        float v = blocks[(size_t)5 * nout * 2 + e];
-        for (int p = 1; p < NQ; ++p) v += blocks[(size_t)(5 + p) * nout * 2 + e];
-        blocks[e] = v;
-    }
-    __syncthreads();
-    for (int mu = 0; mu < 4; ++mu) {
-        int c[4], r = i;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            c[m] = r % a.na[m];
-            r /= a.na[m];
-        }
-        c[mu] = (c[mu] - 1 + a.na[mu]) % a.na[mu];
-        const int j = c[0] + a.na[0] * (c[1] + a.na[1] * (c[2] + a.na[2] * c[3]));
-        const float *src = a.Dc + ((size_t)j * 9 + 1 + mu) * nout * 2;
-        float *dst = blocks + (size_t)(5 + mu) * nout * 2;
-        for (int e = threadIdx.x; e < nout; e += blockDim.x) {
-            const int row = e / N2, col = e - row * N2;
-            const float s = ((row < a.N) == (col < a.N)) ? 1.f : -1.f;
-            const int t = col * N2 + row;
-            dst[2 * e] = s * src[2 * t];
-            dst[2 * e + 1] = -s * src[2 * t + 1];
         }
     }
 }
@@ -359,11 +335,12 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     if (!a.Q || !a.Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
     if (op->Va > MAXVA) return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate volume above 256");
-    const size_t lds = sizeof(SiteRef) * 2 * MAXVA + sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv);
-    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, NQ + 4), dim3(NTHR), lds, st, a, links, clover);
-    if (int rc = hip_check(hipGetLastError(), "k_coarse launch")) return rc;
-    hipLaunchKernelGGL((k_coarse_finish<Tq>), dim3(op->n_agg), dim3(NTHR), 0, st, a);
-    return hip_check(hipGetLastError(), "k_coarse_finish launch");
+    for (int mu = 0; mu < 4; ++mu)
+        if (op->Va / op->g.agg[mu] > MAXFACE)
+            return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate face above 64 sites");
+    const size_t lds = sizeof(SiteRef) * (MAXVA + MAXFACE) + sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv + 2);
+    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a, links, clover);
+    return hip_check(hipGetLastError(), "k_coarse launch");
 }
 
 }  // namespace

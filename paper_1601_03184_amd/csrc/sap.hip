@@ -34,6 +34,11 @@ template <typename Ts, typename Tc> struct SapArgs {
     const Ts *b;
     const Ts *xr;           // where neighbours' x is read (x itself, or a snapshot)
     Ts *x;
+    // sigma = b - D_j x_j per block, kept between the visits of a colour (arithmetic type):
+    // the residual of a later visit is sigma - (hops across the block's faces)
+    Tc *sig;
+    int sig_in;             // this colour's sigma is valid (read it instead of forming b - D x)
+    int sig_out;            // write sigma for the next visit of this colour
     // even-odd block solver: A^-1 per site (clover layout), block offsets in parity order,
     // number of even sites of a block
     const Tc *cloverinv;
@@ -193,16 +198,22 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
         }
     }
 
-    // 1. residual on the block
+    // 1. residual on the block: b - D x, or sigma - (face hops) once sigma is known
+    const int colour = a.colour, mode = a.mode;
+    const uint32_t *bcs = a.blk_coords;
+    auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
     if (active) {
         Spinor<Tc> r;
         if (a.mode != 0) {
-            const int colour = a.colour, mode = a.mode;
-            const uint32_t *bcs = a.blk_coords;
-            auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
-            dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
             Spinor<Tc> bb;
-            load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+            if (a.sig_in) {
+                spinor_zero(r);
+                face_hops_global<Tc>(g, a.links, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+                load_spinor<Tc>(g, a.sig, grp, blk, off, tt, bb);
+            } else {
+                dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+                load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+            }
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 r.re[c] = bb.re[c] - r.re[c];
@@ -301,6 +312,30 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
             }
         }
         store_spinor(g, a.x, grp, blk, off, tt, e);
+    }
+    // 4. sigma for the next visit: b - D_j x_j(new) = rho (the block residual after the MR
+    //    steps, this lane's own LDS slot) + the face hops, which this half-sweep leaves unchanged
+    if (active && a.sig_out) {
+        Spinor<Tc> sg;
+        if (a.mode != 0) {
+            // the coordinates are decoded again rather than kept live through the MR steps
+            int bc2[4], lc2[4];
+            decode_site(g, a.blk_coords, a.loc_coords, blk, opaque_index(off), bc2, lc2);
+            spinor_zero(sg);
+            face_hops_global<Tc>(g, a.links, a.xr, grp, tt, blk, off, bc2, lc2, sg, skip);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const P2 o = rho[c * str + me];
+            if (a.mode != 0) {
+                sg.re[c] += o.x;
+                sg.im[c] += o.y;
+            } else {
+                sg.re[c] = o.x;
+                sg.im[c] = o.y;
+            }
+        }
+        store_spinor(g, a.sig, grp, blk, off, tt, sg);
     }
 }
 
@@ -699,6 +734,8 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
             snap[k] = (Ts *)wp;
             wp += align256(native_elems(op, n_rhs[k]) * sizeof(Ts));
         }
+        a.sig = (Tc *)wp;
+        wp += align256(native_elems(op, n_rhs[k]) * sizeof(Tc));
     }
     for (int s = 0; s < n_sap; ++s)
         for (int c = 0; c < 2; ++c) {
@@ -711,6 +748,9 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
                 a.blocks = op->colour_blocks + (c == 0 ? 0 : op->n_colour[0]);
                 a.nblocks = op->n_colour[c];
                 a.mode = s == 0 && !guess ? c : 2;  // from zero, x vanishes on blocks not yet visited
+                // sigma carries a colour's residual from one visit to the next (plain MR only)
+                a.sig_in = !eo && s > 0;
+                a.sig_out = !eo && s + 1 < n_sap;
                 a.xr = a.x;
                 if (a.mode == 2 && op->odd_blocks) {
                     C.src[C.n_inst] = a.x;
@@ -755,8 +795,11 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
 size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs)
 {
     size_t w = 0;
-    for (int k = 0; k < n; ++k)
-        if (ops[k]->odd_blocks) w += align256(native_elems(ops[k], n_rhs[k]) * dtype_size(ops[k]->dtype));
+    for (int k = 0; k < n; ++k) {
+        const size_t ne = native_elems(ops[k], n_rhs[k]);
+        if (ops[k]->odd_blocks) w += align256(ne * dtype_size(ops[k]->dtype));
+        w += align256(ne * (ops[k]->prec == MRHS_PREC_F64 ? sizeof(double) : sizeof(float)));  // sigma
+    }
     return w;
 }
 

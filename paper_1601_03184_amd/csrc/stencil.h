@@ -177,6 +177,54 @@ __device__ inline void dirac_site_global(const KGeo &g, const Tf *__restrict__ l
     hop_fence(out);
 }
 
+// out += the hops of (D x)(site) whose neighbour lies outside the site's SAP block (the
+// part of the residual that couples a block to its neighbours); SKIP as above.
+template <typename Tc, typename Ts, typename Tf, typename Skip>
+__device__ inline void face_hops_global(const KGeo &g, const Tf *__restrict__ links, const Ts *__restrict__ x, int grp,
+                                        int t, int blk, int off, const int (&bc)[4], const int (&lc)[4],
+                                        Spinor<Tc> &out, Skip skip)
+{
+    const long ns = (long)blk * g.Vb + off;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        hop_fence(out);
+        // forward neighbour across the +mu face
+        if (lc[mu] + 1 == g.b[mu] && g.nb[mu] > 1) {
+            const NbrSite n = nbr_fwd(g, mu, blk, off, bc, lc);
+            if (!skip(n.blk)) {
+                Spinor<typename ChiType<Tc, Ts>::type> chi;
+                load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
+                Tc U[18];
+                load_link(links, g.V, mu, ns, U);
+                switch (mu) {
+                case 0: hop_accumulate<0, -1, false>(U, chi, out); break;
+                case 1: hop_accumulate<1, -1, false>(U, chi, out); break;
+                case 2: hop_accumulate<2, -1, false>(U, chi, out); break;
+                default: hop_accumulate<3, -1, false>(U, chi, out); break;
+                }
+            }
+        }
+        hop_fence(out);
+        // backward neighbour across the -mu face
+        if (lc[mu] == 0 && g.nb[mu] > 1) {
+            const NbrSite n = nbr_bwd(g, mu, blk, off, bc, lc);
+            if (!skip(n.blk)) {
+                Spinor<typename ChiType<Tc, Ts>::type> chi;
+                load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
+                Tc U[18];
+                load_link(links, g.V, mu, (long)n.blk * g.Vb + n.off, U);
+                switch (mu) {
+                case 0: hop_accumulate<0, +1, true>(U, chi, out); break;
+                case 1: hop_accumulate<1, +1, true>(U, chi, out); break;
+                case 2: hop_accumulate<2, +1, true>(U, chi, out); break;
+                default: hop_accumulate<3, +1, true>(U, chi, out); break;
+                }
+            }
+        }
+    }
+    hop_fence(out);
+}
+
 struct NoSkip {
     __device__ bool operator()(int) const { return false; }
 };
