@@ -432,6 +432,60 @@ def refinement_bench(mr, m=8, tol=0.05, reps=10):
             "restrict_speedup": round(t_r1 / t_r, 2)}
 
 
+def coarse_grid_c5(mr, m=8, tol=0.05, reps=5):
+    """The coarse grid of the headline workload (41472 coarse sites, 2 N_tv = 64 dof): the
+    coarse-operator apply on the N_tv restricted test vectors and the low-accuracy coarse
+    GMRES (m = 8, tolerance 0.05), with D_c (and the Krylov basis) in FP32 and in binary16
+    (the half-precision coarse grid); the GMRES also replayed from a captured graph.
+    Algorithmic bytes of an apply: D_c once plus the vectors of a site and its 8 neighbours
+    (read once, written once: 2 x the coarse vectors, the neighbours' from cache)."""
+    op, n = mr.op, mr.n
+    nc = 2 * n
+    bc, uc, zc = op.coarse_empty(n, n), op.coarse_empty(n, n), op.coarse_empty(n, n)
+    mrhs.restrict_mrhs(op.handle, mr.Q, mrhs.DTYPE_F32, n, mr.x, op.dtype, bc, n)
+    D16 = torch.empty(op.n_agg * 9 * nc * nc * 2, dtype=torch.float16, device="cuda")
+    t_b16 = time_call(lambda: mrhs.coarse_op_build_f16(op.handle, mr.Q, mrhs.DTYPE_F32, n, D16), 2, warmup=1)
+    cvb = bc.numel() * 4
+    out = {"coarse_op_build_f16_ms": round(t_b16, 3)}
+    for name, D, app, dcb in (("f32", mr.Dc, mrhs.coarse_apply_mrhs, mr.Dc.numel() * 4),
+                              ("f16", D16, mrhs.coarse_apply_f16_mrhs, D16.numel() * 2)):
+        ms = time_call(lambda: app(op.handle, D, n, bc, zc, n), reps)
+        byts = dcb + 2 * cvb
+        out["apply_" + name] = {"ms": round(ms, 4), "alg_bytes": byts, "alg_GBs": round(byts / ms / 1e6, 1),
+                                "frac_hbm": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    for name, D, solve, wsf in (("f32", mr.Dc, mrhs.coarse_solve_mrhs, mrhs.mrhs_coarse_solve_workspace_bytes),
+                                ("f16", D16, mrhs.coarse_solve_f16_mrhs, mrhs.mrhs_coarse_solve_f16_workspace_bytes)):
+        ws = torch.empty(wsf(op.handle, n, n, m), dtype=torch.uint8, device="cuda")
+        res = torch.zeros(n, dtype=torch.float64, device="cuda")
+        its = torch.zeros(n, dtype=torch.int32, device="cuda")
+        fn = lambda stream=None: solve(op.handle, D, n, bc, uc, n, m, tol, ws, res, its, stream=stream)
+        ms = time_call(fn, reps)
+        fn()
+        torch.cuda.synchronize()
+        it = int(its.max().item())
+        # the true relative residual ||b - D_c u|| / ||b|| with the FP32 operator
+        mrhs.coarse_apply_mrhs(op.handle, mr.Dc, n, uc, zc, n)
+        ldc = (n + 3) // 4 * 4
+        r = (bc - zc).view(-1, ldc).double()
+        true = float((r.pow(2).sum(0).sqrt() / bc.view(-1, ldc).double().pow(2).sum(0).sqrt())[:n].max().item())
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                fn(stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        ms_g = time_call(g.replay, reps)
+        out["gmres_" + name] = {"ms": round(ms, 3), "graph_replay_ms": round(ms_g, 3), "iterations": it,
+                                "ms_per_iteration": round(ms / max(it, 1), 3),
+                                "workspace_bytes": ws.numel(), "residual_estimate_max": float(res.max().item()),
+                                "true_residual_max": true}
+        del ws, g
+    del D16
+    torch.cuda.empty_cache()
+    return out
+
+
 def extras_16(args):
     """The 16^4 workload (N_tv 20): its step, and the extras built on it."""
     cfg = C2
@@ -638,6 +692,7 @@ def main():
     ap.add_argument("--no-srhs", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the 16^4 extras and the batch")
+    ap.add_argument("--no-coarse", action="store_true", help="skip the coarse grid of the headline workload")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-refine", action="store_true")
     ap.add_argument("--no-eo", action="store_true")
@@ -709,6 +764,12 @@ def main():
                 "alg_tflops": round(sap_flops_per_call(V, n, N_SAP, N_MR, BLOCK) / per["sap"] / 1e9, 3)}
     log("roofline %s; stencil %s; copy %s" % (roof, stencil, copy))
 
+    coarse5 = None
+    if not args.no_coarse:
+        log("coarse grid of the headline workload (FP32 and half precision)")
+        coarse5 = coarse_grid_c5(mr)
+        log("coarse %s" % coarse5)
+
     host = None
     if not args.no_cpu_baseline:
         log("copying the sampled results to the host")
@@ -766,6 +827,7 @@ def main():
         "stencil_roofline": stencil,
         "copy_ceiling": copy,
         "sap": sap_info,
+        "coarse_grid": coarse5,
         "accuracy": acc,
         "srhs": srhs,
         "fp16_storage_32x32x32x64": fp16,

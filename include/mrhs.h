@@ -216,6 +216,28 @@ int coarse_solve_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const fl
                       int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
                       void *stream);
 
+/* ---- the half-precision coarse grid (storage precision reduced on the coarse grid, as the
+ * DD-alpha-AMG implementation the paper builds on does, Sec. 1; arithmetic stays FP32) ----
+ * Dc16: D_c stored in IEEE binary16, the same layout and element order as coarse_op_build's
+ * complex64 (a (re, im) pair of binary16 per entry, 8 N^2 bytes per block): half the bytes
+ * that every coarse-operator apply reads.  Entries above 65504 in modulus would overflow
+ * (D_c of a Wilson-clover operator is O(1)); the relative rounding error of an entry is at
+ * most 2^-11.
+ * coarse_op_build_f16: as coarse_op_build, each entry rounded once from its FP32 sum.
+ * coarse_apply_f16_mrhs: as coarse_apply_mrhs with D_c from Dc16 (FP32 vectors and FP32
+ *   accumulation on the matrix cores).
+ * coarse_solve_f16_mrhs: as coarse_solve_mrhs with D_c from Dc16 and the Krylov basis stored
+ *   in binary16 (each basis vector rounded once when formed; inner products, the Hessenberg
+ *   matrix and the rotations stay FP64, the working vector FP32); bc, uc FP32.  ws: at least
+ *   mrhs_coarse_solve_f16_workspace_bytes(op, n_tv, n_rhs, m) bytes. */
+int coarse_op_build_f16(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc16, void *stream);
+int coarse_apply_f16_mrhs(const mrhs_op *op, const void *Dc16, int32_t n_tv, const float *yc, float *yc_out,
+                          int32_t n_rhs, void *stream);
+size_t mrhs_coarse_solve_f16_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m);
+int coarse_solve_f16_mrhs(const mrhs_op *op, const void *Dc16, int32_t n_tv, const float *bc, float *uc, int32_t n_rhs,
+                          int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
+                          void *stream);
+
 /* Even-odd preconditioned coarse solve (the coarse-grid counterpart of DD-alpha-AMG's even-odd
  * preconditioning).  Coarse sites split by the parity of their coordinate sum; every coarse
  * extent L/agg must be even, so each of the 8 hop blocks joins sites of opposite parity:

@@ -388,7 +388,16 @@ int coarse_op_build(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n
     if (int rc = check_dtype(q_dtype)) return rc;
     (void)ws;
     (void)ws_bytes;
-    return launch_coarse(op, Q, q_dtype, n_tv, Dc, (hipStream_t)stream);
+    return launch_coarse(op, Q, q_dtype, n_tv, Dc, MRHS_DTYPE_F32, (hipStream_t)stream);
+}
+
+int coarse_op_build_f16(const mrhs_op *op, const void *Q, int32_t q_dtype, int32_t n_tv, void *Dc16, void *stream)
+{
+    if (int rc = check_op(op)) return rc;
+    if (int rc = check_nrhs(n_tv)) return rc;
+    if (!Q || !Dc16) return set_error(MRHS_EINVAL, "null argument");
+    if (int rc = check_dtype(q_dtype)) return rc;
+    return launch_coarse(op, Q, q_dtype, n_tv, Dc16, MRHS_DTYPE_F16, (hipStream_t)stream);
 }
 
 size_t mrhs_coarse_vector_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs)
@@ -449,6 +458,42 @@ int coarse_apply_mrhs(const mrhs_op *op, const float *Dc, int32_t n_tv, const fl
         ranges_overlap(yc_out, cb, Dc, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(float)))
         return set_error(MRHS_EINVAL, "coarse output overlaps an input");
     return launch_coarse_apply(op, Dc, n_tv, yc, yc_out, n_rhs, (hipStream_t)stream);
+}
+
+int coarse_apply_f16_mrhs(const mrhs_op *op, const void *Dc16, int32_t n_tv, const float *yc, float *yc_out,
+                          int32_t n_rhs, void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, MRHS_DTYPE_F32)) return rc;
+    if (!Dc16 || !yc || !yc_out) return set_error(MRHS_EINVAL, "null argument");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    if (ranges_overlap(yc_out, cb, yc, cb) ||
+        ranges_overlap(yc_out, cb, Dc16, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(__half)))
+        return set_error(MRHS_EINVAL, "coarse output overlaps an input");
+    return launch_coarse_apply_f16(op, (const __half *)Dc16, n_tv, yc, yc_out, n_rhs, (hipStream_t)stream);
+}
+
+size_t mrhs_coarse_solve_f16_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m)
+{
+    if (!op || n_tv <= 0 || n_rhs <= 0 || m <= 0) return 0;
+    return ws_bytes_coarse_solve_f16(op, n_tv, n_rhs, m);
+}
+
+int coarse_solve_f16_mrhs(const mrhs_op *op, const void *Dc16, int32_t n_tv, const float *bc, float *uc, int32_t n_rhs,
+                          int32_t m, double tol, double *res_out, int32_t *iters_out, void *ws, size_t ws_bytes,
+                          void *stream)
+{
+    if (int rc = check_transfer(op, n_tv, n_rhs, MRHS_DTYPE_F32)) return rc;
+    if (!Dc16 || !bc || !uc) return set_error(MRHS_EINVAL, "null argument");
+    if (m < 1 || m > 64) return set_error(MRHS_EINVAL, "iteration count must be 1..64");
+    if (!(tol >= 0.0)) return set_error(MRHS_EINVAL, "tolerance must be >= 0");
+    const size_t need = ws_bytes_coarse_solve_f16(op, n_tv, n_rhs, m);
+    if (!ws || ws_bytes < need) return set_error(MRHS_EINVAL, "workspace too small");
+    const size_t cb = mrhs_coarse_vector_bytes(op, n_tv, n_rhs);
+    if (ranges_overlap(uc, cb, bc, cb) || ranges_overlap(uc, cb, ws, need) || ranges_overlap(bc, cb, ws, need) ||
+        ranges_overlap(uc, cb, Dc16, (size_t)op->n_agg * 9 * 4 * n_tv * n_tv * 2 * sizeof(__half)))
+        return set_error(MRHS_EINVAL, "coarse vectors overlap each other, D_c or the workspace");
+    return launch_coarse_solve_f16(op, (const __half *)Dc16, n_tv, bc, uc, n_rhs, m, tol, res_out, iters_out, ws,
+                                   (hipStream_t)stream);
 }
 
 size_t mrhs_coarse_solve_workspace_bytes(const mrhs_op *op, int32_t n_tv, int32_t n_rhs, int32_t m)

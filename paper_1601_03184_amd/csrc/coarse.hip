@@ -37,7 +37,8 @@ template <typename Tq> struct CoarseArgs {
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
-    float *Dc;  // [n_agg][9][2N][2N][2]
+    float *Dc;       // [n_agg][9][2N][2N][2], or null with
+    __half *Dc16;    // the same in binary16 (each entry rounded once from the FP32 sum)
 };
 
 // A site the workgroup touches: native index (fields), offset of its first element within a
@@ -281,8 +282,11 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     }
     // D_c(i, i) or D_c(i, i + mu); for a face also D_c(i + mu, i) = sigma3 D_c(i, i + mu)^dag sigma3
     // into the -mu slot of aggregate j = i + mu (each slot has exactly one writer)
-    float *out = a.Dc + ((size_t)i * 9 + d) * N2 * N2 * 2;
-    float *bwd = a.Dc + ((size_t)j * 9 + 5 + mu) * N2 * N2 * 2;
+    const size_t ob = ((size_t)i * 9 + d) * N2 * N2 * 2, bb = ((size_t)j * 9 + 5 + mu) * N2 * N2 * 2;
+    auto put = [&](size_t e, float v) {
+        if (a.Dc16) a.Dc16[e] = __float2half_rn(v);
+        else a.Dc[e] = v;
+    };
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) {
         const int tile = wave + NW * m;
@@ -295,13 +299,13 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             if (k < N && c < N2) {
                 const int row = h * N + k;
                 const size_t e = (size_t)row * N2 + c;
-                out[2 * e] = accr[m][r];
-                out[2 * e + 1] = acci[m][r];
+                put(ob + 2 * e, accr[m][r]);
+                put(ob + 2 * e + 1, acci[m][r]);
                 if (!self) {
                     const float sg = ((row < N) == (c < N)) ? 1.f : -1.f;
                     const size_t t = (size_t)c * N2 + row;
-                    bwd[2 * t] = sg * accr[m][r];
-                    bwd[2 * t + 1] = -sg * acci[m][r];
+                    put(bb + 2 * t, sg * accr[m][r]);
+                    put(bb + 2 * t + 1, -sg * acci[m][r]);
                 }
             }
         }
@@ -309,7 +313,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
 }
 
 template <typename Tc, typename Tq>
-int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc,
+int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const Tq *Q, int n_tv, void *Dc, bool f16,
                     hipStream_t st)
 {
     CoarseArgs<Tq> a{};
@@ -331,8 +335,9 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.blk_coords = op->blk_coords;
     a.loc_coords = op->loc_coords;
     a.Q = Q;
-    a.Dc = (float *)Dc;
-    if (!a.Q || !a.Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
+    a.Dc = f16 ? nullptr : (float *)Dc;
+    a.Dc16 = f16 ? (__half *)Dc : nullptr;
+    if (!a.Q || !Dc || !a.agg_sites || !a.blk_coords || !a.loc_coords || !links || !clover)
         return set_error(MRHS_EINVAL, "coarse_op_build: missing buffer");
     if (op->Va > MAXVA) return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate volume above 256");
     for (int mu = 0; mu < 4; ++mu)
@@ -347,19 +352,20 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
 
 size_t ws_bytes_coarse(const mrhs_op *, int) { return 0; }
 
-int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st)
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, int dcdt, hipStream_t st)
 {
+    const bool f16 = dcdt == MRHS_DTYPE_F16;
     if (2 * n_tv * 2 * n_tv > 16 * NTHR) return set_error(MRHS_EUNSUPPORTED, "more than 32 test vectors");
     if (op->links32) {
         if (qdt == MRHS_DTYPE_F32)
-            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, st);
+            return coarse_dispatch<float, float>(op, op->links32, op->clover32, (const float *)Q, n_tv, Dc, f16, st);
         if (qdt == MRHS_DTYPE_F16)
-            return coarse_dispatch<float, __half>(op, op->links32, op->clover32, (const __half *)Q, n_tv, Dc, st);
-        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, st);
+            return coarse_dispatch<float, __half>(op, op->links32, op->clover32, (const __half *)Q, n_tv, Dc, f16, st);
+        return coarse_dispatch<float, double>(op, op->links32, op->clover32, (const double *)Q, n_tv, Dc, f16, st);
     }
     if (qdt == MRHS_DTYPE_F32)
-        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, st);
+        return coarse_dispatch<double, float>(op, op->links64, op->clover64, (const float *)Q, n_tv, Dc, f16, st);
     if (qdt == MRHS_DTYPE_F16)
-        return coarse_dispatch<double, __half>(op, op->links64, op->clover64, (const __half *)Q, n_tv, Dc, st);
-    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, st);
+        return coarse_dispatch<double, __half>(op, op->links64, op->clover64, (const __half *)Q, n_tv, Dc, f16, st);
+    return coarse_dispatch<double, double>(op, op->links64, op->clover64, (const double *)Q, n_tv, Dc, f16, st);
 }

@@ -5,12 +5,15 @@
 // operator is applied to all of them in one coarse_apply (the mat-mat form of Sec. 6).
 //
 // Vectors are FP32 (coarse layout of transfer.hip); inner products, norms, the Hessenberg
-// matrix, the rotations and the small triangular solve are FP64.  A right-hand side whose
+// matrix, the rotations and the small triangular solve are FP64.  The half-precision coarse
+// grid keeps the Krylov basis in binary16 (each basis vector rounded once when it is formed;
+// a FP32 copy of the newest one feeds the operator) and D_c in binary16.  A right-hand side whose
 // residual estimate has reached tol * ||b|| stops taking part (its later basis vectors are
 // zero and its Hessenberg matrix is frozen), so the host issues a fixed sequence of
 // launches without reading anything back.
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "launch.h"
 
@@ -31,7 +34,8 @@ struct GmArgs {
     long dim;     // complex entries per right-hand side (coarse sites x 2 n_tv)
     long cvlen;   // floats of one coarse vector
     double tol;
-    float *V;     // (m + 1) coarse vectors
+    void *V;      // (m + 1) coarse vectors, FP32 or binary16 (the basis type of gmres_run)
+    float *v32;   // binary16 basis: the newest basis vector as FP32 (input of the operator)
     float *w;
     Z *part;      // [vectors][G][ldc] partial inner products, G x vectors <= GPART
     Z *hcur;      // [ldc][m + 1]: the current inner products, then y
@@ -105,18 +109,19 @@ __device__ void gm_givens(const GmArgs &a, int k, int j, double nw2)
 
 // part[i][blk][k] = sum over this block's chunk of entries of conj(X_i) y, for the vectors
 // X_i = X + i * xstride (i = blockIdx.y) and every right-hand side k
-__global__ void __launch_bounds__(DTHR) k_gm_dots(GmArgs a, const float *X, long xstride, const float *y)
+template <typename TX>
+__global__ void __launch_bounds__(DTHR) k_gm_dots(GmArgs a, const TX *X, long xstride, const float *y)
 {
     __shared__ Z red[DROWS][32];
     const int G = gridDim.x, i = blockIdx.y;
     const int k = threadIdx.x & 31, row = threadIdx.x >> 5;
     const long chunk = (a.dim + G - 1) / G, e0 = blockIdx.x * chunk, e1 = e0 + chunk < a.dim ? e0 + chunk : a.dim;
-    const float *xi = X + i * xstride;
+    const TX *xi = X + i * xstride;
     Z s = {0.0, 0.0};
     if (k < a.ldc)
         for (long e = e0 + row; e < e1; e += DROWS) {
             const long o = cre(a, e, k);
-            const Z xv = {xi[o], xi[o + a.ldc]}, yv = {y[o], y[o + a.ldc]};
+            const Z xv = {load_as<double>(xi + o), load_as<double>(xi + o + a.ldc)}, yv = {y[o], y[o + a.ldc]};
             const Z p = zconjmul(xv, yv);
             s.re += p.re;
             s.im += p.im;
@@ -186,7 +191,7 @@ int gm_blocks(const GmArgs &a, int nvec)
 }
 
 // w -= sum_i hcur[k][i] V_i   (i < nvec)
-__global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
+template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.dim * a.ldc) return;
@@ -196,8 +201,8 @@ __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
     double wr = a.w[o], wi = a.w[o + a.ldc];
     for (int i = 0; i < nvec; ++i) {
         const Z h = a.hcur[(long)k * (a.m + 1) + i];
-        const float *vi = a.V + i * a.cvlen;
-        const Z v = {vi[o], vi[o + a.ldc]};
+        const TV *vi = (const TV *)a.V + i * a.cvlen;
+        const Z v = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
         const Z p = zmul(h, v);
         wr -= p.re;
         wi -= p.im;
@@ -206,8 +211,8 @@ __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
     a.w[o + a.ldc] = (float)wi;
 }
 
-// V_dst = src * scale[k]
-__global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, float *dst)
+// V_dst = src * scale[k] (rounded to the basis type); dst32 (nullable): the same values as FP32
+template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, TV *dst, float *dst32)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.dim * a.ldc) return;
@@ -215,8 +220,13 @@ __global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, f
     const int k = (int)(t - e * a.ldc);
     const long o = cre(a, e, k);
     const double s = a.scale[k];
-    dst[o] = (float)(src[o] * s);
-    dst[o + a.ldc] = (float)(src[o + a.ldc] * s);
+    const TV re = store_as<TV>((float)(src[o] * s)), im = store_as<TV>((float)(src[o + a.ldc] * s));
+    dst[o] = re;
+    dst[o + a.ldc] = im;
+    if (dst32) {
+        dst32[o] = load_as<float>(&re);
+        dst32[o + a.ldc] = load_as<float>(&im);
+    }
 }
 
 // y = H^-1 g (back substitution over the J[k] iterations taken), into hcur
@@ -247,7 +257,7 @@ __global__ void k_gm_solve(GmArgs a, double *res_out, int32_t *iters_out)
 }
 
 // u = sum_i y_i V_i
-__global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
+template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.dim * a.ldc) return;
@@ -258,8 +268,8 @@ __global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
     const int J = a.J[k];
     for (int i = 0; i < J; ++i) {
         const Z y = a.hcur[(long)k * (a.m + 1) + i];
-        const float *vi = a.V + i * a.cvlen;
-        const Z v = {vi[o], vi[o + a.ldc]};
+        const TV *vi = (const TV *)a.V + i * a.cvlen;
+        const Z v = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
         const Z p = zmul(y, v);
         ur += p.re;
         ui += p.im;
@@ -270,8 +280,9 @@ __global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 
-// workspace layout for (op, n_tv, n, m); fills the pointers when base != nullptr
-size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *a)
+// workspace layout for (op, n_tv, n, m); fills the pointers when base != nullptr.  vsz: bytes
+// of a basis element (4, or 2 for a binary16 basis, which also takes a FP32 vector v32)
+size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *a, int vsz = 4)
 {
     const int ldc = (n + 3) / 4 * 4;
     const long dim = (long)op->n_agg * 2 * n_tv;
@@ -282,7 +293,8 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
         off += align256(bytes);
         return p;
     };
-    char *V = take(sizeof(float) * cvlen * (m + 1));
+    char *V = take((size_t)vsz * cvlen * (m + 1));
+    char *v32 = vsz == 4 ? nullptr : take(sizeof(float) * cvlen);
     char *w = take(sizeof(float) * cvlen);
     char *part = take(sizeof(Z) * (size_t)GPART * ldc);
     char *hcur = take(sizeof(Z) * (size_t)ldc * (m + 1));
@@ -301,7 +313,8 @@ size_t gm_layout(const mrhs_op *op, int n_tv, int n, int m, char *base, GmArgs *
         a->m = m;
         a->dim = dim;
         a->cvlen = cvlen;
-        a->V = (float *)V;
+        a->V = V;
+        a->v32 = (float *)v32;
         a->w = (float *)w;
         a->part = (Z *)part;
         a->hcur = (Z *)hcur;
@@ -411,42 +424,47 @@ __global__ void k_inv_status_final(int *s)
     if (*s == INT_MAX) *s = 0;
 }
 
-// GMRES on all right-hand sides for the operator apply(in, out) (coarse vectors), from b into u
-template <typename Apply>
+// GMRES on all right-hand sides for the operator apply(in, out) (coarse vectors), from b into u;
+// TV: the basis type (float, or __half for the half-precision coarse grid)
+template <typename TV, typename Apply>
 int gmres_run(GmArgs &a, const float *b, float *u, int m, double *res_out, int32_t *iters_out, Apply apply,
               hipStream_t st)
 {
     const long nel = a.dim * a.ldc;
     const int eb = (int)((nel + GTHR - 1) / GTHR);
     const int kb = (a.ldc + 63) / 64;
+    TV *V = (TV *)a.V;
 #define GM_CHECK(what) \
     if (int rc = hip_check(hipGetLastError(), what)) return rc
-    auto dots = [&](const float *X, long xstride, int nvec, const float *y, int col, int step) {
+    auto dots = [&](auto X, long xstride, int nvec, const float *y, int col, int step) {
+        using TX = std::remove_const_t<std::remove_pointer_t<decltype(X)>>;
         const int G = gm_blocks(a, nvec);
-        hipLaunchKernelGGL(k_gm_dots, dim3(G, nvec), dim3(DTHR), 0, st, a, X, xstride, y);
+        hipLaunchKernelGGL(k_gm_dots<TX>, dim3(G, nvec), dim3(DTHR), 0, st, a, X, xstride, y);
         if (int rc = hip_check(hipGetLastError(), "k_gm_dots launch")) return rc;
         hipLaunchKernelGGL(k_gm_finish, dim3((nvec * a.ldc * FR + 255) / 256), dim3(256), 0, st, a, G, nvec, col, step);
         return hip_check(hipGetLastError(), "k_gm_finish launch");
     };
     // beta, V_0
     if (int rc = dots(b, 0L, 1, b, 0, GM_START)) return rc;
-    hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, b, a.V);
+    hipLaunchKernelGGL(k_gm_scale<TV>, dim3(eb), dim3(GTHR), 0, st, a, b, V, a.v32);
     GM_CHECK("k_gm_scale launch");
     for (int j = 0; j < m; ++j) {
-        float *vj = a.V + (long)j * a.cvlen;
-        if (int rc = apply((const float *)vj, a.w)) return rc;
+        // the operator's input: the basis vector itself, or its FP32 copy for a binary16 basis
+        const float *vj = a.v32 ? a.v32 : (const float *)(V + (long)j * a.cvlen);
+        if (int rc = apply(vj, a.w)) return rc;
         for (int pass = 0; pass < 2; ++pass) {
-            if (int rc = dots(a.V, a.cvlen, j + 1, a.w, j, GM_PROJECT)) return rc;
-            hipLaunchKernelGGL(k_gm_axpy, dim3(eb), dim3(GTHR), 0, st, a, j + 1);
+            if (int rc = dots((const TV *)V, a.cvlen, j + 1, a.w, j, GM_PROJECT)) return rc;
+            hipLaunchKernelGGL(k_gm_axpy<TV>, dim3(eb), dim3(GTHR), 0, st, a, j + 1);
             GM_CHECK("k_gm_axpy launch");
         }
-        if (int rc = dots(a.w, 0L, 1, a.w, j, GM_NORM)) return rc;
-        hipLaunchKernelGGL(k_gm_scale, dim3(eb), dim3(GTHR), 0, st, a, (const float *)a.w, a.V + (long)(j + 1) * a.cvlen);
+        if (int rc = dots((const float *)a.w, 0L, 1, a.w, j, GM_NORM)) return rc;
+        hipLaunchKernelGGL(k_gm_scale<TV>, dim3(eb), dim3(GTHR), 0, st, a, (const float *)a.w, V + (long)(j + 1) * a.cvlen,
+                           a.v32);
         GM_CHECK("k_gm_scale launch");
     }
     hipLaunchKernelGGL(k_gm_solve, dim3(kb), dim3(64), 0, st, a, res_out, iters_out);
     GM_CHECK("k_gm_solve launch");
-    hipLaunchKernelGGL(k_gm_combine, dim3(eb), dim3(GTHR), 0, st, a, u);
+    hipLaunchKernelGGL(k_gm_combine<TV>, dim3(eb), dim3(GTHR), 0, st, a, u);
     GM_CHECK("k_gm_combine launch");
 #undef GM_CHECK
     return MRHS_OK;
@@ -468,7 +486,22 @@ int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const floa
     gm_layout(op, n_tv, n, m, (char *)ws, &a);
     a.tol = tol;
     auto apply = [&](const float *in, float *out) { return launch_coarse_apply(op, Dc, n_tv, in, out, n, st); };
-    return gmres_run(a, b, u, m, res_out, iters_out, apply, st);
+    return gmres_run<float>(a, b, u, m, res_out, iters_out, apply, st);
+}
+
+size_t ws_bytes_coarse_solve_f16(const mrhs_op *op, int n_tv, int n, int m)
+{
+    return gm_layout(op, n_tv, n, m, nullptr, nullptr, 2);
+}
+
+int launch_coarse_solve_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *b, float *u, int n, int m,
+                            double tol, double *res_out, int32_t *iters_out, void *ws, hipStream_t st)
+{
+    GmArgs a{};
+    gm_layout(op, n_tv, n, m, (char *)ws, &a, 2);
+    a.tol = tol;
+    auto apply = [&](const float *in, float *out) { return launch_coarse_apply_f16(op, Dc16, n_tv, in, out, n, st); };
+    return gmres_run<__half>(a, b, u, m, res_out, iters_out, apply, st);
 }
 
 size_t ws_bytes_coarse_solve_eo(const mrhs_op *op, int n_tv, int n, int m)
@@ -531,7 +564,7 @@ int launch_coarse_solve_eo(const mrhs_op *op, const float *Dc, const float *Dinv
         if (int rc = ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, true, t2)) return rc;
         return ap(Dc, 9, nullptr, in, t2, -1.f, 0, true, out);
     };
-    if (int rc = gmres_run(a, bh, u, m, res_out, iters_out, schur, st)) return rc;
+    if (int rc = gmres_run<float>(a, bh, u, m, res_out, iters_out, schur, st)) return rc;
     // u_o = A_oo^-1 (b - H u)_o, the even sites of u kept
     if (int rc = ap(Dc, 9, b, nullptr, u, -1.f, 1, true, t1)) return rc;
     return ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, false, u);

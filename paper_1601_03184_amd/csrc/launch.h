@@ -18,7 +18,8 @@ int launch_residual(const mrhs_op *op, const void *b, const void *x, int n_rhs, 
 int launch_residual_noalloc(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, hipStream_t st);
 int launch_gs(const mrhs_op *op, const void *V, int vdt, void *Q, int qdt, int n_tv, int32_t *status, void *ws,
               hipStream_t st);
-int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, hipStream_t st);
+// D_c into Dc as complex64 (dcdt MRHS_DTYPE_F32) or as binary16 pairs (MRHS_DTYPE_F16)
+int launch_coarse(const mrhs_op *op, const void *Q, int qdt, int n_tv, void *Dc, int dcdt, hipStream_t st);
 size_t ws_bytes_sap(const mrhs_op *op, int n_rhs);
 size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_rhs);
 int launch_sap_batched(const mrhs_op *const *ops, int n, const void *const *b, void *const *x, const int32_t *n_rhs,
@@ -40,6 +41,9 @@ int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const floa
 int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
                            const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
                            hipStream_t st);
+// yco = D_c yc with D_c stored in binary16 (as written by launch_coarse with MRHS_DTYPE_F16)
+int launch_coarse_apply_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *yc, float *yco, int n,
+                            hipStream_t st);
 size_t transfer_lds_bytes(const mrhs_op *op);
 // even-odd preconditioned coarse solve and the self-block inverses it uses
 size_t ws_bytes_coarse_solve_eo(const mrhs_op *op, int n_tv, int n, int m);
@@ -48,6 +52,10 @@ int launch_coarse_self_inverse(const mrhs_op *op, const float *Dc, int n_tv, flo
 int launch_coarse_solve_eo(const mrhs_op *op, const float *Dc, const float *Dinv, int n_tv, const float *b, float *u,
                            int n, int m, double tol, double *res_out, int32_t *iters_out, void *ws, hipStream_t st);
 size_t ws_bytes_coarse_solve(const mrhs_op *op, int n_tv, int n, int m);
+// the half-precision coarse grid: D_c and the Krylov basis in binary16, FP32 arithmetic
+size_t ws_bytes_coarse_solve_f16(const mrhs_op *op, int n_tv, int n, int m);
+int launch_coarse_solve_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *b, float *u, int n, int m,
+                            double tol, double *res_out, int32_t *iters_out, void *ws, hipStream_t st);
 int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const float *b, float *u, int n, int m, double tol,
                         double *res_out, int32_t *iters_out, void *ws, hipStream_t st);
 size_t ws_bytes_refine(const mrhs_op *op, int n_tv, int m);

@@ -248,7 +248,8 @@ __global__ void __launch_bounds__(TTHR) k_prolong(TransArgs a)
 struct CApplyArgs {
     int na[4];
     int Vc, N, n, ldc;
-    const float *Dc;     // [Vc][nblk][2N][2N][2]
+    const float *Dc;     // [Vc][nblk][2N][2N][2], or null with
+    const __half *Dc16;  // the same stored in binary16 (arithmetic stays FP32)
     int nblk;            // 9 (self, +x..+t, -x..-t) or 1 (self only)
     const float *yself;  // input of the self block (null: no self term)
     const float *yhop;   // input of the 8 hop blocks (null: no hop term)
@@ -307,13 +308,21 @@ template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CA
         const int j = cn[0] + a.na[0] * (cn[1] + a.na[1] * (cn[2] + a.na[2] * cn[3]));
         float br[KS], bi[KS];
         if (use) {
-            const float *blk = a.Dc + ((size_t)i * a.nblk + d) * N2 * N2 * 2 + (size_t)16 * tr * N2 * 2;
+            const size_t blk = ((size_t)i * a.nblk + d) * N2 * N2 * 2 + (size_t)16 * tr * N2 * 2;
             const float *yj = ysrc + (size_t)j * N2 * 2 * a.ldc;
-            // the 16-row slab of the block (contiguous) into LDS
-            const int nq = rows_here * a.N;  // float4 per row: 2 N2 / 4 = N
+            // the 16-row slab of the block (contiguous) into LDS, four reals per load
+            const int nq = rows_here * a.N;  // four reals per load, 2 N2 / 4 = N per row
             for (int q = tk * 64 + lane; q < nq; q += 64 * TK) {
                 const int rr = q / a.N, c4 = q - rr * a.N;
-                const float4 v = ((const float4 *)blk)[q];
+                float4 v;
+                if (a.Dc16) {
+                    const uint2 u = ((const uint2 *)(a.Dc16 + blk))[q];
+                    const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&u.x));
+                    const float2 hi = __half22float2(*reinterpret_cast<const __half2 *>(&u.y));
+                    v = make_float4(lo.x, lo.y, hi.x, hi.y);
+                } else {
+                    v = ((const float4 *)(a.Dc + blk))[q];
+                }
                 *(float2 *)&sl[rr * RS + 4 * c4] = make_float2(v.x, v.y);
                 *(float2 *)&sl[rr * RS + 4 * c4 + 2] = make_float2(v.z, v.w);
             }
@@ -453,11 +462,14 @@ int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const floa
     return launch_coarse_apply_ex(op, Dc, 9, n_tv, nullptr, yc, yc, 1.f, -1, false, yco, n, st);
 }
 
-int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
-                           const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
-                           hipStream_t st)
+namespace {
+
+int coarse_apply_any(const mrhs_op *op, const float *Dc, const __half *Dc16, int nblk, int n_tv, const float *y0,
+                     const float *yself, const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
+                     hipStream_t st)
 {
     CApplyArgs a{};
+    a.Dc16 = Dc16;
     for (int mu = 0; mu < 4; ++mu) a.na[mu] = op->na[mu];
     a.Vc = op->n_agg;
     a.N = n_tv;
@@ -474,4 +486,19 @@ int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_t
     a.yco = yco;
     if (n_tv < 1 || n_tv > 32 || n < 1 || n > 32) return set_error(MRHS_EUNSUPPORTED, "coarse apply: n_tv and n must be 1..32");
     return coarse_apply_ks<1>(a, (2 * n_tv + 3) / 4, st);
+}
+
+}  // namespace
+
+int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
+                           const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
+                           hipStream_t st)
+{
+    return coarse_apply_any(op, Dc, nullptr, nblk, n_tv, y0, yself, yhop, s_hop, parity, zero_other, yco, n, st);
+}
+
+int launch_coarse_apply_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *yc, float *yco, int n,
+                            hipStream_t st)
+{
+    return coarse_apply_any(op, nullptr, Dc16, 9, n_tv, nullptr, yc, yc, 1.f, -1, false, yco, n, st);
 }

@@ -69,6 +69,10 @@ def lib():
             "mrhs_coarse_solve_workspace_bytes": (sz, [p, i32, i32, i32]),
             "coarse_solve_mrhs": (i32, [p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
             "coarse_self_invert": (i32, [p, p, i32, p, p, p]),
+            "coarse_op_build_f16": (i32, [p, p, i32, i32, p, p]),
+            "coarse_apply_f16_mrhs": (i32, [p, p, i32, p, p, i32, p]),
+            "mrhs_coarse_solve_f16_workspace_bytes": (sz, [p, i32, i32, i32]),
+            "coarse_solve_f16_mrhs": (i32, [p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
             "mrhs_coarse_solve_eo_workspace_bytes": (sz, [p, i32, i32, i32]),
             "coarse_solve_eo_mrhs": (i32, [p, p, p, i32, p, p, i32, i32, d, p, p, p, sz, p]),
             "mrhs_refine_workspace_bytes": (sz, [p, i32, i32]),
@@ -207,6 +211,25 @@ def coarse_solve_mrhs(op, Dc, n_tv, bc, uc, n_rhs, m, tol, ws, res_out=None, ite
     nb = ws.numel() * ws.element_size() if ws is not None else 0
     _check(lib().coarse_solve_mrhs(op, _dptr(Dc), int(n_tv), _dptr(bc), _dptr(uc), int(n_rhs), int(m), float(tol),
                                    _dptr(res_out), _dptr(iters_out), _dptr(ws), nb, _stream(stream)))
+
+
+def coarse_op_build_f16(op, Q, q_dtype, n_tv, Dc16, stream=None):
+    _check(lib().coarse_op_build_f16(op, _dptr(Q), int(q_dtype), int(n_tv), _dptr(Dc16), _stream(stream)))
+
+
+def coarse_apply_f16_mrhs(op, Dc16, n_tv, yc, yc_out, n_rhs, stream=None):
+    _check(lib().coarse_apply_f16_mrhs(op, _dptr(Dc16), int(n_tv), _dptr(yc), _dptr(yc_out), int(n_rhs),
+                                       _stream(stream)))
+
+
+def mrhs_coarse_solve_f16_workspace_bytes(op, n_tv, n_rhs, m):
+    return lib().mrhs_coarse_solve_f16_workspace_bytes(op, int(n_tv), int(n_rhs), int(m))
+
+
+def coarse_solve_f16_mrhs(op, Dc16, n_tv, bc, uc, n_rhs, m, tol, ws, res_out=None, iters_out=None, stream=None):
+    nb = ws.numel() * ws.element_size() if ws is not None else 0
+    _check(lib().coarse_solve_f16_mrhs(op, _dptr(Dc16), int(n_tv), _dptr(bc), _dptr(uc), int(n_rhs), int(m), float(tol),
+                                       _dptr(res_out), _dptr(iters_out), _dptr(ws), nb, _stream(stream)))
 
 
 def coarse_self_invert(op, Dc, n_tv, Dinv, status=None, stream=None):

@@ -245,3 +245,30 @@ def test_coarse_gmres_exact_and_minimal():
     for k in range(3):
         _, r_prev, _ = oracle.coarse_gmres(L, a, Dc, bc[k:k + 1], m=int(its[k]) - 1)
         assert its[k] == 1 or r_prev[0] > 0.5
+
+
+def test_fp16_storage_of_dc_tolerance(setup_vectors):
+    """The tolerance of the half-precision coarse grid, derived on the oracle: D_c rounded to
+    IEEE binary16 (round to nearest even, unit roundoff u = 2^-11) perturbs every entry by at
+    most u relative, so the coarse apply of any vector moves by at most u || |D_c| |y| ||;
+    for these diagonally dominated blocks that is a few u relative per right-hand side, well
+    inside the 5e-3 stated for FP16 storage.  Checked in FP64 on random coarse vectors."""
+    U, A, x = setup_vectors
+    Q = oracle.block_gs(L4, A2, x)
+    Dc = oracle.coarse_op(L4, A2, U, A, Q)
+    D16 = Dc.real.astype(np.float16).astype(np.float64) + 1j * Dc.imag.astype(np.float16).astype(np.float64)
+    u = 2.0 ** -11
+    assert np.all(np.abs(D16.real - Dc.real) <= u * np.abs(Dc.real) + 6e-8)
+    assert np.all(np.abs(D16.imag - Dc.imag) <= u * np.abs(Dc.imag) + 6e-8)
+    rng = np.random.default_rng(5)
+    n, Vc, N = 4, Dc.shape[0], Dc.shape[-1] // 2
+    y = rng.standard_normal((n, Vc, 2, N)) + 1j * rng.standard_normal((n, Vc, 2, N))
+    ref = oracle.coarse_apply(L4, A2, Dc, y)
+    got = oracle.coarse_apply(L4, A2, D16, y)
+    # |D| |y| entry-wise (moduli), and |delta D_ij| <= sqrt(2) u |D_ij|
+    bound = oracle.coarse_apply(L4, A2, np.abs(Dc) + 0j, np.abs(y) + 0j).real
+    err = np.linalg.norm((got - ref).reshape(n, -1), axis=1) / np.linalg.norm(ref.reshape(n, -1), axis=1)
+    rb = np.linalg.norm(bound.reshape(n, -1), axis=1) / np.linalg.norm(ref.reshape(n, -1), axis=1)
+    assert np.all(err <= np.sqrt(2) * u * rb * 1.001)
+    assert np.all(err < 5e-3)
+    assert np.all(rb < 10)
