@@ -3,7 +3,8 @@
 //
 // Column c = (h', k') of P is q_k' restricted to spin half h' on each aggregate.  Per
 // coarse site i the 9 stored blocks are
-//   self: Q_i^dag (A + hops that stay inside the aggregate) P_i
+//   self: Q_i^dag (A + hops that stay inside the aggregate) P_i, formed as G + sigma3 G^dag sigma3
+//         with G = Q_i^dag (A/2 + forward hops that stay inside) P_i
 //   +mu : Q_i^dag (1 - g_mu) W_mu P_{i+mu} over the sites on the +mu face   (W = -U/2)
 //   -mu : sigma3 (+mu block of i-mu)^dag sigma3
 // The last line is exact: the -mu face hop of i is the adjoint of the +mu face hop of i-mu
@@ -83,9 +84,10 @@ __device__ inline void load_half(const Tq *__restrict__ qk, uint32_t vo, uint32_
     }
 }
 
+// w += the forward hop in direction MU when the neighbour x + mu lies in the same aggregate
 template <int MU, int HP, typename Tc, typename Tq>
-__device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const SiteRef *tab,
-                                   const SiteRef &me, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
+__device__ inline void inside_fwd_hop(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const SiteRef *tab,
+                                      const SiteRef &me, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
 {
     const int l = unpack_coord(me.lc, MU);
     if (l + 1 < a.a[MU]) {
@@ -97,15 +99,6 @@ __device__ inline void inside_hops(const CoarseArgs<Tq> &a, const Tc *__restrict
         hop_accumulate<MU, -1, false>(U, chi, w);
     }
     hop_fence(w);
-    if (l > 0) {
-        const SiteRef n = tab[ls - a.astr[MU]];
-        Spinor<Tc> chi;
-        load_half<HP, Tc>(qk, n.vo, cs, chi);
-        Tc U[18];
-        load_link(links, a.g.V, MU, n.ns, U);
-        hop_accumulate<MU, +1, true>(U, chi, w);
-    }
-    hop_fence(w);
 }
 
 // local site of the f-th site on the +mu face of an aggregate (local coordinate mu = a_mu - 1)
@@ -115,7 +108,10 @@ __device__ inline int face_site(const int (&a)[4], const int (&astr)[4], int mu,
     return f % st + st * (a[mu] - 1) + st * a[mu] * (f / st);
 }
 
-// column (HP, k') of the self part at aggregate site ls: (A + hops that stay inside) P_c
+// column (HP, k') of half the self part at aggregate site ls: (A / 2 + the forward hops that
+// stay inside) P_c.  The backward inside hops are g5 (forward hops)^dag g5 and A is
+// Hermitian and commutes with g5, so with G = Q^dag (A/2 + forward inside hops) P the self
+// block is G + sigma3 G^dag sigma3 (g5 P = P sigma3).
 template <int HP, typename Tc, typename Tq>
 __device__ inline void self_column(const CoarseArgs<Tq> &a, const Tc *__restrict__ links, const Tc *__restrict__ clover,
                                    const SiteRef *tab, int ls, const Tq *qk, uint32_t cs, Spinor<Tc> &w)
@@ -130,11 +126,16 @@ __device__ inline void self_column(const CoarseArgs<Tq> &a, const Tc *__restrict
         load_clover_half<HP>(clover, a.g.V, me.ns, A);
         clover_half<HP>(A, p, w);
     }
+#pragma unroll
+    for (int c = 6 * HP; c < 6 * HP + 6; ++c) {
+        w.re[c] *= Tc(0.5);
+        w.im[c] *= Tc(0.5);
+    }
     hop_fence(w);
-    inside_hops<0, HP>(a, links, tab, me, ls, qk, cs, w);
-    inside_hops<1, HP>(a, links, tab, me, ls, qk, cs, w);
-    inside_hops<2, HP>(a, links, tab, me, ls, qk, cs, w);
-    inside_hops<3, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_fwd_hop<0, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_fwd_hop<1, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_fwd_hop<2, HP>(a, links, tab, me, ls, qk, cs, w);
+    inside_fwd_hop<3, HP>(a, links, tab, me, ls, qk, cs, w);
 }
 
 // column (HP, k') of the +MU face part at face site f: (1 - g_mu) W_mu P_c(x + mu), the
@@ -287,6 +288,34 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
         if (a.Dc16) a.Dc16[e] = __float2half_rn(v);
         else a.Dc[e] = v;
     };
+    if (self) {
+        // D_c(i, i) = G + sigma3 G^dag sigma3: G through LDS (over the chunk buffers, free once
+        // every wavefront has finished its last products), then written row by row
+        const int GST = N2 + 1;
+        float2 *Gs = Qs;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < MAXT; ++m) {
+            const int tile = wave + NW * m;
+            if (tile >= ntile) break;
+            const int h = tile / (TR * TC), rem = tile - h * TR * TC, tr = rem / TC, tc = rem - tr * TC;
+            const int c = tc * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int k = tr * 16 + 4 * (lane >> 4) + r;
+                if (k < N && c < N2) Gs[(h * N + k) * GST + c] = make_float2(accr[m][r], acci[m][r]);
+            }
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < N2 * N2; e += NTHR) {
+            const int row = e / N2, c = e - row * N2;
+            const float2 g = Gs[row * GST + c], t = Gs[c * GST + row];
+            const float sg = ((row < N) == (c < N)) ? 1.f : -1.f;
+            put(ob + 2 * (size_t)e, g.x + sg * t.x);
+            put(ob + 2 * (size_t)e + 1, g.y - sg * t.y);
+        }
+        return;
+    }
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) {
         const int tile = wave + NW * m;

@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "stencil.h"
 
 namespace {
 
@@ -261,6 +262,9 @@ struct CApplyArgs {
 };
 
 constexpr int CA_GROUPS = 3;
+#ifndef CA_SITE_MIN
+#define CA_SITE_MIN 1024
+#endif
 constexpr int CA_MAXTHR = 64 * CA_GROUPS * 2;  // two right-hand-side tiles (n <= 32)
 
 template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CApplyArgs a)
@@ -376,6 +380,212 @@ template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CA
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// coarse apply for large coarse lattices: one workgroup per coarse site, wavefront w owning
+// output rows 16w .. 16w + 15 for every right-hand side (up to two 16-column tiles).  For each
+// direction the neighbour's coarse vector (2N rows x n right-hand sides) is staged in LDS once
+// for all the wavefronts, re/im interleaved per right-hand side, double-buffered so that the
+// next direction's copy is in flight during this one's products; each wavefront reads its
+// 16-row slab of the direction's block straight into registers (read once per apply, so with
+// non-temporal loads), the next direction's slab also in flight.  The order of the columns
+// inside a contraction is free: lane (r = l % 16, g = l / 16) loads columns 2(g + 4q) and
+// 2(g + 4q) + 1 of row r with one 16-byte load (8 bytes in binary16), and matrix-core step
+// (q, h) contracts column 2(g + 4q) + h.  Sites are taken in XCD-contiguous runs, so the
+// neighbours along x and y of a site are staged by workgroups of the same XCD close in time.
+// ---------------------------------------------------------------------------------------
+constexpr int CS_YRS = 36;   // LDS row stride of a staged vector, complex entries (32 + 4 of padding)
+constexpr int CS_ROWS = 64;  // 2N <= 64
+
+template <typename TD> struct SlabLoad;
+template <> struct SlabLoad<float> {
+    using raw = f4;
+    static __device__ inline raw load(const float *p) { return __builtin_nontemporal_load((const f4 *)p); }
+    static __device__ inline f4 expand(raw v) { return v; }
+};
+template <> struct SlabLoad<__half> {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    using raw = u2;
+    static __device__ inline raw load(const __half *p) { return __builtin_nontemporal_load((const u2 *)p); }
+    static __device__ inline f4 expand(raw v)
+    {
+        const unsigned int x = v.x, y = v.y;
+        const float2 lo = __half22float2(*reinterpret_cast<const __half2 *>(&x));
+        const float2 hi = __half22float2(*reinterpret_cast<const __half2 *>(&y));
+        return f4{lo.x, lo.y, hi.x, hi.y};
+    }
+};
+
+template <typename TD, int QN, int TK> __global__ void __launch_bounds__(256) k_coarse_apply_site(CApplyArgs a)
+{
+    __shared__ float2 ys[2][CS_ROWS * CS_YRS];
+    using SL = SlabLoad<TD>;
+    const int N2 = 2 * a.N, nthr = blockDim.x;
+    const int i = xcd_remap(blockIdx.x, a.Vc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
+    int c[4], rem = i;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        c[m] = rem % a.na[m];
+        rem /= a.na[m];
+    }
+    const int row = 16 * w + r;
+    float *out = a.yco + (size_t)i * N2 * 2 * a.ldc;
+    if (a.parity >= 0 && ((c[0] + c[1] + c[2] + c[3]) & 1) != a.parity) {
+        // a site of the other parity (uniform over the workgroup, before any barrier)
+        if (a.zero_other)
+            for (int tk = 0; tk < TK; ++tk)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int orow = 16 * w + 4 * g + q, k = 16 * tk + r;
+                    if (orow < N2 && k < a.ldc) {
+                        out[(size_t)(2 * orow) * a.ldc + k] = 0.f;
+                        out[(size_t)(2 * orow + 1) * a.ldc + k] = 0.f;
+                    }
+                }
+        return;
+    }
+    const int nk4 = a.ldc / 4, items = N2 * nk4;  // staging items: 4 right-hand sides of one row
+    // neighbour of direction d, its vector (null: no term) and the sign of its term
+    auto src_of = [&](int d, float &sgn) -> const float * {
+        const float *ysrc = d == 0 ? a.yself : a.yhop;
+        sgn = d == 0 ? 1.f : a.s_hop;
+        if (!ysrc) return nullptr;
+        int cn[4] = {c[0], c[1], c[2], c[3]};
+        if (d >= 1 && d <= 4) cn[d - 1] = (cn[d - 1] + 1) % a.na[d - 1];
+        if (d >= 5) cn[d - 5] = (cn[d - 5] - 1 + a.na[d - 5]) % a.na[d - 5];
+        const int j = cn[0] + a.na[0] * (cn[1] + a.na[1] * (cn[2] + a.na[2] * cn[3]));
+        return ysrc + (size_t)j * N2 * 2 * a.ldc;
+    };
+    // staging registers: at most two items per thread (items <= 16 N <= 2 x threads)
+    f4 yre[2], yim[2];
+    auto stage_load = [&](const float *src) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int it = threadIdx.x + u * nthr;
+            if (it < items) {
+                const int cr = it / nk4, k4 = it - cr * nk4;
+                yre[u] = *(const f4 *)(src + (size_t)(2 * cr) * a.ldc + 4 * k4);
+                yim[u] = *(const f4 *)(src + (size_t)(2 * cr + 1) * a.ldc + 4 * k4);
+            }
+        }
+    };
+    auto stage_store = [&](float2 *dst, float sgn) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int it = threadIdx.x + u * nthr;
+            if (it < items) {
+                const int cr = it / nk4, k4 = it - cr * nk4;
+                f4 *p = (f4 *)(dst + cr * CS_YRS + 4 * k4);
+                p[0] = f4{sgn * yre[u].x, sgn * yim[u].x, sgn * yre[u].y, sgn * yim[u].y};
+                p[1] = f4{sgn * yre[u].z, sgn * yim[u].z, sgn * yre[u].w, sgn * yim[u].w};
+            }
+        }
+    };
+    typename SL::raw A[QN], An[QN];
+    auto slab_load = [&](int d, typename SL::raw (&dst)[QN]) {
+        const size_t base = (((size_t)i * a.nblk + d) * N2 + row) * N2 * 2;
+        const TD *D = a.Dc16 ? (const TD *)a.Dc16 : (const TD *)a.Dc;
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const int c2 = g + 4 * q;
+            if (row < N2 && c2 < a.N) dst[q] = SL::load(D + base + 4 * c2);
+            else dst[q] = typename SL::raw{};
+        }
+    };
+    f4 dr[2], di[2];
+#pragma unroll
+    for (int tk = 0; tk < 2; ++tk) dr[tk] = di[tk] = f4{0.f, 0.f, 0.f, 0.f};
+
+    float sgn0;
+    const float *s0 = src_of(0, sgn0);
+    if (s0) {
+        stage_load(s0);
+        slab_load(0, A);
+        stage_store(ys[0], sgn0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int d = 0; d < a.nblk; ++d) {
+        float sgn_c, sgn_n = 1.f;
+        const bool cur = src_of(d, sgn_c) != nullptr;
+        const float *sn = d + 1 < a.nblk ? src_of(d + 1, sgn_n) : nullptr;
+        if (sn) {
+            stage_load(sn);
+            slab_load(d + 1, An);
+        }
+        if (cur) {
+            const float2 *yb = ys[d & 1];
+            // four independent accumulator chains between dependent matrix-core steps: the two
+            // right-hand-side tiles, or with one tile its two accumulator pairs (alternate
+            // column steps, added at the end)
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                const f4 v = SL::expand(A[q]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int col = 2 * (g + 4 * q) + h;
+                    const float ar = h ? v.z : v.x, ai = h ? v.w : v.y;
+                    float2 b[2];
+#pragma unroll
+                    for (int tk = 0; tk < 2; ++tk) {
+                        const int k = 16 * (TK == 2 ? tk : 0) + r;
+                        b[tk] = {0.f, 0.f};
+                        if (col < N2 && k < a.n) b[tk] = yb[col * CS_YRS + k];
+                    }
+                    if (TK == 2) {
+                        dr[0] = mfma32(ar, b[0].x, dr[0]);
+                        di[0] = mfma32(ar, b[0].y, di[0]);
+                        dr[1] = mfma32(ar, b[1].x, dr[1]);
+                        di[1] = mfma32(ar, b[1].y, di[1]);
+                        dr[0] = mfma32(-ai, b[0].y, dr[0]);
+                        di[0] = mfma32(ai, b[0].x, di[0]);
+                        dr[1] = mfma32(-ai, b[1].y, dr[1]);
+                        di[1] = mfma32(ai, b[1].x, di[1]);
+                    } else {
+                        const int u = h;  // alternate pairs of accumulators by column step
+                        dr[u] = mfma32(ar, b[0].x, dr[u]);
+                        di[u] = mfma32(ar, b[0].y, di[u]);
+                        dr[u] = mfma32(-ai, b[0].y, dr[u]);
+                        di[u] = mfma32(ai, b[0].x, di[u]);
+                    }
+                }
+            }
+        }
+        if (sn) stage_store(ys[(d + 1) & 1], sgn_n);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QN; ++q) A[q] = An[q];
+    }
+    if (TK == 1) {
+        dr[0] += dr[1];
+        di[0] += di[1];
+    }
+    const float *o0 = a.y0 ? a.y0 + (size_t)i * N2 * 2 * a.ldc : nullptr;
+    for (int tk = 0; tk < TK; ++tk)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int orow = 16 * w + 4 * g + q, k = 16 * tk + r;
+            if (orow < N2 && k < a.ldc) {
+                const size_t e = (size_t)(2 * orow) * a.ldc + k;
+                const bool kok = k < a.n;
+                const float ar = o0 ? o0[e] : 0.f, ai = o0 ? o0[e + a.ldc] : 0.f;
+                out[e] = kok ? ar + (tk ? dr[1][q] : dr[0][q]) : 0.f;
+                out[e + a.ldc] = kok ? ai + (tk ? di[1][q] : di[0][q]) : 0.f;
+            }
+        }
+}
+
+template <typename TD, int QN> int coarse_apply_site_q(const CApplyArgs &a, int qn, hipStream_t st)
+{
+    if constexpr (QN < 8) {
+        if (qn > QN) return coarse_apply_site_q<TD, QN + 1>(a, qn, st);
+    }
+    const int waves = (2 * a.N + 15) / 16;
+    if (a.n > 16) hipLaunchKernelGGL((k_coarse_apply_site<TD, QN, 2>), dim3(a.Vc), dim3(64 * waves), 0, st, a);
+    else hipLaunchKernelGGL((k_coarse_apply_site<TD, QN, 1>), dim3(a.Vc), dim3(64 * waves), 0, st, a);
+    return hip_check(hipGetLastError(), "k_coarse_apply_site launch");
+}
+
 // KS = ceil(2N / 4) = 1 .. 16 (n_tv <= 32)
 template <int KS> int coarse_apply_ks(const CApplyArgs &a, int ks, hipStream_t st)
 {
@@ -485,6 +695,12 @@ int coarse_apply_any(const mrhs_op *op, const float *Dc, const __half *Dc16, int
     a.zero_other = zero_other ? 1 : 0;
     a.yco = yco;
     if (n_tv < 1 || n_tv > 32 || n < 1 || n > 32) return set_error(MRHS_EUNSUPPORTED, "coarse apply: n_tv and n must be 1..32");
+    // many coarse sites: one workgroup per site; few: one per (site, 16-row tile), which
+    // gives the chip more workgroups
+    if (a.Vc >= CA_SITE_MIN) {
+        const int qn = (n_tv + 3) / 4;
+        return Dc16 ? coarse_apply_site_q<__half, 1>(a, qn, st) : coarse_apply_site_q<float, 1>(a, qn, st);
+    }
     return coarse_apply_ks<1>(a, (2 * n_tv + 3) / 4, st);
 }
 
