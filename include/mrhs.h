@@ -143,9 +143,9 @@ int mrhs_residual_norms(const mrhs_op *op, const void *b, const void *x, int32_t
  * kernels, with their partial sums in a static 32 MiB scratch array of the library instead
  * of ws.  Each device holds one copy of the array until the process ends; the first call on
  * a device looks up its address (no allocation).  The call allocates nothing and never
- * synchronises.  The partial sums of n_rhs right-hand sides take ceil(n_rhs/S)*S * n_blocks
- * * 16 bytes; larger requests return MRHS_EUNSUPPORTED (at 48^3 x 96 with 4^4 blocks: up to
- * 50 right-hand sides).  All calls on one device share the array and it keeps the last
+ * synchronises.  The partial sums take 16 bytes per block and right-hand side, n_rhs rounded
+ * up to a multiple of 8 (short length 4; of S otherwise); larger requests return
+ * MRHS_EUNSUPPORTED (at 48^3 x 96 with 4^4 blocks: up to 48 right-hand sides).  All calls on one device share the array and it keeps the last
  * call's partial sums: calls that overlap in time on one device (other streams, other
  * threads) race and give wrong norms; the caller serialises them. */
 int mrhs_residual_norms_noalloc(const mrhs_op *op, const void *b, const void *x, int32_t n_rhs, double *out,

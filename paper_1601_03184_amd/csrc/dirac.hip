@@ -41,9 +41,10 @@ __global__ void __launch_bounds__(256 * T) k_dirac(KGeo g, const Tc *__restrict_
 
 // Per (block, tile of T right-hand sides): partial sums of |b - D x|^2 and |b|^2 per
 // right-hand side, FP64.  A workgroup of (up to 64 sites) x T lanes walks the block in
-// passes of 64 sites, so that a workgroup is small (256 threads at T = 4) while the FP64
-// stencil takes ~130 registers: three workgroups share a CU instead of one.  The T lanes of
-// a site share its FP64 field loads.
+// passes of 64 sites, so that a workgroup is small while the FP64 stencil takes ~130
+// registers.  The T lanes of a site share its FP64 field loads; with T = 2S a tile spans two
+// groups of the native layout (lanes t < S the first, t >= S the second), which halves the
+// field loads per right-hand side.  Lanes of a group beyond the last one add nothing.
 constexpr int RES_SITES = 64;
 
 template <typename Ts, int T>
@@ -52,18 +53,18 @@ __global__ void __launch_bounds__(RES_SITES * T) k_residual(KGeo g, const double
                                                             const uint32_t *__restrict__ blk_coords,
                                                             const uint32_t *__restrict__ loc_coords,
                                                             const Ts *__restrict__ b, const Ts *__restrict__ x,
-                                                            int ntiles, double *__restrict__ part)
+                                                            int ntiles, int ngrp, double *__restrict__ part)
 {
     __shared__ double red[RES_SITES * T / 64][T][2];
     // tiles of one block on one XCD, consecutively: the block's FP64 fields and its
     // neighbours' spinors are fetched into that XCD's L2 once for all its tiles
     const int li = xcd_remap(blockIdx.x, g.nblk * ntiles);
     const int blk = li / ntiles, tile = li - blk * ntiles;
-    const int grp = (tile * T) / g.S, tt = (tile * T) % g.S + threadIdx.x % T;  // T divides S: grp is uniform
+    const int lt = tile * T + threadIdx.x % T, grp = lt / g.S, tt = lt % g.S;
     const int nsite = g.Vb < RES_SITES ? g.Vb : RES_SITES;
     double num = 0, den = 0;
 #pragma unroll 1
-    for (int o = threadIdx.x / T; o < g.Vb; o += nsite) {
+    for (int o = threadIdx.x / T; o < g.Vb && grp < ngrp; o += nsite) {
         const int off = opaque_index(o);
         int bc[4], lc[4];
         decode_site(g, blk_coords, loc_coords, blk, off, bc, lc);
@@ -154,28 +155,39 @@ int dirac_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const v
     return hip_check(hipGetLastError(), "k_dirac launch");
 }
 
+// lanes per site of the residual: two groups of 4 right-hand sides, else as many lanes as
+// the short length allows
+int residual_tile(const KGeo &g) { return g.S % 4 == 0 ? 8 : g.S % 2 == 0 ? 2 : 1; }
+int residual_tiles(const KGeo &g, int n_rhs, int T)
+{
+    const int ngrp = (n_rhs + g.S - 1) / g.S;
+    return (ngrp * g.S + T - 1) / T;
+}
+
 template <typename Ts, int T>
 int residual_launch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
 {
     const KGeo &g = op->k;
     const int ngrp = (n_rhs + g.S - 1) / g.S;
-    const int ntiles = ngrp * (g.S / T);
+    const int ntiles = residual_tiles(g, n_rhs, T);
     double *part = (double *)ws;
     const int nsite = g.Vb < RES_SITES ? g.Vb : RES_SITES;
     hipLaunchKernelGGL((k_residual<Ts, T>), dim3(g.nblk * ntiles), dim3(round64(nsite * T)), 0, st, g, op->links64,
-                       op->clover64, op->blk_coords, op->loc_coords, (const Ts *)b, (const Ts *)x, ntiles, part);
+                       op->clover64, op->blk_coords, op->loc_coords, (const Ts *)b, (const Ts *)x, ntiles, ngrp,
+                       part);
     if (int rc = hip_check(hipGetLastError(), "k_residual launch")) return rc;
     hipLaunchKernelGGL((k_residual_finish<T>), dim3(n_rhs), dim3(256), 0, st, part, g.nblk, n_rhs, out);
     return hip_check(hipGetLastError(), "k_residual_finish launch");
 }
 
-// as many lanes per site as the short length allows (up to 4)
 template <typename Ts>
 int residual_dispatch(const mrhs_op *op, const void *b, const void *x, int n_rhs, double *out, void *ws, hipStream_t st)
 {
-    if (op->k.S % 4 == 0) return residual_launch<Ts, 4>(op, b, x, n_rhs, out, ws, st);
-    if (op->k.S % 2 == 0) return residual_launch<Ts, 2>(op, b, x, n_rhs, out, ws, st);
-    return residual_launch<Ts, 1>(op, b, x, n_rhs, out, ws, st);
+    switch (residual_tile(op->k)) {
+    case 8: return residual_launch<Ts, 8>(op, b, x, n_rhs, out, ws, st);
+    case 2: return residual_launch<Ts, 2>(op, b, x, n_rhs, out, ws, st);
+    default: return residual_launch<Ts, 1>(op, b, x, n_rhs, out, ws, st);
+    }
 }
 
 }  // namespace
@@ -195,8 +207,8 @@ int launch_dirac(const mrhs_op *op, const void *x, void *y, int n_rhs, hipStream
 size_t ws_bytes_residual(const mrhs_op *op, int n_rhs)
 {
     const KGeo &g = op->k;
-    const int ngrp = (n_rhs + g.S - 1) / g.S;
-    return (size_t)ngrp * g.S * g.nblk * 2 * sizeof(double);
+    const int T = residual_tile(g);
+    return (size_t)residual_tiles(g, n_rhs, T) * T * g.nblk * 2 * sizeof(double);
 }
 
 namespace {

@@ -7,7 +7,7 @@
 //   G1 = V^dag V = R1^dag R1,  Q1 = V R1^-1,  G2 = Q1^dag Q1 = R2^dag R2,  Q = V (R1^-1 R2^-1),
 // the thin QR factor with a real positive triangular diagonal (the Q that Gram-Schmidt
 // with re-orthogonalisation produces).  The products V^dag V, V M and Q1^dag Q1 run on
-// v_mfma_f64_16x16x4f64 (16x16 output tiles, complex = 4 real products, only the upper
+// v_mfma_f64_16x16x4f64 (16x16 output tiles, complex = 3 real products, only the upper
 // tiles of a Hermitian product, only the non-zero K steps of a triangular one); the
 // Cholesky factorisations and triangular inverses of the n_tv x n_tv matrices run on the
 // vector units in LDS and registers.
@@ -155,14 +155,23 @@ __device__ void tri_product(const Cplx *A, const Cplx *B, Cplx *C, int NP)
     __syncthreads();
 }
 
-// Gram accumulators of the tile pairs (0,0), (0,1), (1,1), real and imaginary part
+// Gram accumulators of the tile pairs (0,0), (0,1), (1,1), real and imaginary part.  A
+// diagonal pair needs three real products per K step, not four: Re = Xr^T Xr + Xi^T Xi,
+// and for the imaginary part only P = Xr^T Xi, whose antisymmetric part P - P^T it is
+// (taken once the wavefronts' tiles are summed, gram_fix_diag); the off-diagonal pair takes
+// Xr^T Xi - Xi^T Xr in full.
 struct GramAcc {
     d4 re[3], im[3];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) re[p] = im[p] = d4{0.0, 0.0, 0.0, 0.0};
+    }
 };
 
 __device__ inline int pair_index(int ti, int tj) { return ti == 0 ? tj : 2; }
 
-// G += x^dag y for one K step, x the operands of the NT column tiles (x = y)
+// G += x^dag x for one K step, x the operands of the NT column tiles
 template <int NT> __device__ inline void gram_step(const double (&xr)[2], const double (&xi)[2], GramAcc &acc)
 {
 #pragma unroll
@@ -173,8 +182,19 @@ template <int NT> __device__ inline void gram_step(const double (&xr)[2], const 
             acc.re[p] = mfma(xr[ti], xr[tj], acc.re[p]);
             acc.re[p] = mfma(xi[ti], xi[tj], acc.re[p]);
             acc.im[p] = mfma(xr[ti], xi[tj], acc.im[p]);
-            acc.im[p] = mfma(-xi[ti], xr[tj], acc.im[p]);
+            if (ti != tj) acc.im[p] = mfma(-xi[ti], xr[tj], acc.im[p]);
         }
+}
+
+// the imaginary part of the diagonal tiles of G from P (upper triangle: P[r][c] - P[c][r])
+template <int NT> __device__ inline void gram_fix_diag(Cplx *G, int NP)
+{
+    for (int e = threadIdx.x; e < NT * 256; e += blockDim.x) {
+        const int t = e >> 8, r = 16 * t + ((e >> 4) & 15), c = 16 * t + (e & 15);
+        if (r < c) G[r * NP + c].im -= G[c * NP + r].im;
+        else if (r == c) G[r * NP + c].im = 0.0;
+    }
+    __syncthreads();
 }
 
 // add (or, for the first wavefront, write) this wavefront's Gram tiles into G
@@ -273,27 +293,34 @@ __device__ inline void load_trans(const Tv *V, const uint32_t *sbase, const size
 }
 
 // tile tj of (the 16 rows) M for upper-triangular M (NP x NP in LDS); the accumulator of
-// tile tj holds rows b0 + l/16 + 4r of columns 16 tj + l%16 in register r
+// tile tj holds rows b0 + l/16 + 4r of columns 16 tj + l%16 in register r.  Three real
+// products per complex one (Gauss): with t1 = Vr Mr, t2 = Vi Mi, t3 = (Vr + Vi)(Mr + Mi),
+// Re V M = t1 - t2 and Im V M = t3 - t1 - t2.
 template <typename Tv, int NT>
 __device__ inline void trans_block(const TransRaw<Tv, NT> &o, const Cplx *M, int NP, int lane, d4 (&dr)[2], d4 (&di)[2])
 {
+    d4 t1[2], t2[2], t3[2];
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj) dr[tj] = di[tj] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int tj = 0; tj < 2; ++tj) t1[tj] = t2[tj] = t3[tj] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < NT * 4; ++ks) {
         const int k = 4 * ks + (lane >> 4);  // column of V = row of M
-        const double vr = to_f64(o.v[ks][0]), vi = to_f64(o.v[ks][1]);
+        const double vr = to_f64(o.v[ks][0]), vi = to_f64(o.v[ks][1]), vs = vr + vi;
 #pragma unroll
         for (int tj = 0; tj < NT; ++tj) {
             if (ks * 4 >= (tj + 1) * 16) continue;  // M is upper triangular
             const Cplx m = M[k * NP + tj * 16 + (lane & 15)];
-            dr[tj] = mfma(vr, m.re, dr[tj]);
-            dr[tj] = mfma(-vi, m.im, dr[tj]);
-            di[tj] = mfma(vr, m.im, di[tj]);
-            di[tj] = mfma(vi, m.re, di[tj]);
+            t1[tj] = mfma(vr, m.re, t1[tj]);
+            t2[tj] = mfma(vi, m.im, t2[tj]);
+            t3[tj] = mfma(vs, m.re + m.im, t3[tj]);
         }
         // one K step at a time: keeps the converted operands of later steps out of registers
         __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+        dr[tj] = t1[tj] - t2[tj];
+        di[tj] = t3[tj] - t1[tj] - t2[tj];
     }
 }
 
@@ -313,7 +340,7 @@ __device__ inline void stage_sites(const GsArgs &a, int i, int ls0, int n, uint3
 // One workgroup per (aggregate i, half h).  Every pass walks the rows in 16-row blocks,
 // NW blocks apart per wavefront, with the next block's elements loaded while the current
 // one is on the matrix cores.
-template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NTHR) k_block_gs(GsArgs a)
+template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;
@@ -340,8 +367,7 @@ template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NT
 
     // G1 = V^dag V
     GramAcc acc;
-#pragma unroll
-    for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
+    acc.zero();
     for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
         const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
         if (staged != ls0) {
@@ -359,13 +385,13 @@ template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NT
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);
+    gram_fix_diag<NT>(G, NP);
     for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = G[k * NP + k].re;
     cholesky_inplace(G, diag0, N, NP, &bad);
     tri_inverse<NP>(G, X1);
 
     // G2 = Q1^dag Q1 with Q1 = V R1^-1 formed block by block on the matrix cores
-#pragma unroll
-    for (int p = 0; p < 3; ++p) acc.re[p] = acc.im[p] = d4{0.0, 0.0, 0.0, 0.0};
+    acc.zero();
     for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
         const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
         if (staged != ls0) {
@@ -408,6 +434,7 @@ template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NT
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);
+    gram_fix_diag<NT>(G, NP);
     for (int k = threadIdx.x; k < NP; k += blockDim.x) diag0[k] = 1.0;
     cholesky_inplace(G, diag0, N, NP, &bad);
     tri_inverse<NP>(G, X2);
