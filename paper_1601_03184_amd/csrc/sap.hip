@@ -63,6 +63,18 @@ __device__ inline void lds_load(const typename LdsPair<Tc>::type *rho, int str, 
     }
 }
 
+// components 6 HF .. 6 HF + 5 (one chiral half) only
+template <int HF, typename Tc>
+__device__ inline void lds_load_half(const typename LdsPair<Tc>::type *rho, int str, int idx, Spinor<Tc> &s)
+{
+#pragma unroll
+    for (int c = 6 * HF; c < 6 * HF + 6; ++c) {
+        const auto v = rho[c * str + idx];
+        s.re[c] = v.x;
+        s.im[c] = v.y;
+    }
+}
+
 template <typename Tc>
 __device__ inline void lds_store(typename LdsPair<Tc>::type *rho, int str, int idx, const Spinor<Tc> &s)
 {
@@ -237,10 +249,22 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
             // the site index is hidden from the compiler so that the block's fields are
             // re-read from cache in every step instead of held in registers across the loop
             const int ns = opaque_index(blk * g.Vb + off);
+            // the clover term one chiral half at a time (it is block-diagonal in them): six
+            // components of rho and 36 field values live instead of twelve and 72
             {
                 Spinor<Tc> own;
-                lds_load<Tc>(rho, str, me, own);
-                clover_site(a.clover, g.V, ns, own, q);
+                Tc A[36];
+                lds_load_half<0, Tc>(rho, str, me, own);
+                load_clover_half<0>(a.clover, g.V, ns, A);
+                clover_half<0>(A, own, q);
+            }
+            hop_fence(q);
+            {
+                Spinor<Tc> own;
+                Tc A[36];
+                lds_load_half<1, Tc>(rho, str, me, own);
+                load_clover_half<1>(a.clover, g.V, ns, A);
+                clover_half<1>(A, own, q);
             }
             hop_fence(q);
             // (the LDS link indices are hidden like ns: the links are re-read in every step)
@@ -491,8 +515,18 @@ __device__ inline void sap_block_eo(const SapArgs<Ts, Tc> &a, int blk, int tile,
             const int ns = opaque_index(blk * g.Vb + se);
             {
                 Spinor<Tc> own;
-                lds_load<Tc>(rho, str, me, own);
-                clover_site(a.clover, g.V, ns, own, q);
+                Tc A[36];
+                lds_load_half<0, Tc>(rho, str, me, own);
+                load_clover_half<0>(a.clover, g.V, ns, A);
+                clover_half<0>(A, own, q);
+            }
+            hop_fence(q);
+            {
+                Spinor<Tc> own;
+                Tc A[36];
+                lds_load_half<1, Tc>(rho, str, me, own);
+                load_clover_half<1>(a.clover, g.V, ns, A);
+                clover_half<1>(A, own, q);
             }
             hop_fence(q);
             eo_hops<Ts, Tc, T>(a, rho, ns, se, t, lce, q);
