@@ -10,7 +10,8 @@
 // a FP32 copy of the newest one feeds the operator) and D_c in binary16.  A right-hand side whose
 // residual estimate has reached tol * ||b|| stops taking part (its later basis vectors are
 // zero and its Hessenberg matrix is frozen), so the host issues a fixed sequence of
-// launches without reading anything back.
+// launches without reading anything back; once no right-hand side takes part, the
+// remaining launches return at once.
 #include <algorithm>
 #include <climits>
 #include <type_traits>
@@ -46,6 +47,16 @@ struct GmArgs {
     double *beta, *est, *scale;  // [ldc]
     int *J, *active;             // [ldc]
 };
+
+// whether any right-hand side still iterates: the kernels of an Arnoldi step return at once
+// when none does, so that the fixed launch sequence costs only the launches after the last
+// right-hand side has stopped
+__device__ inline bool gm_running(const GmArgs &a)
+{
+    bool any = false;
+    for (int k = 0; k < a.n; ++k) any |= a.active[k] != 0;
+    return any;
+}
 
 // element (e, k) of a coarse vector: entry e = site * 2 n_tv + dof, right-hand side k
 __device__ inline long cre(const GmArgs &a, long e, int k) { return (2 * e) * a.ldc + k; }
@@ -110,9 +121,10 @@ __device__ void gm_givens(const GmArgs &a, int k, int j, double nw2)
 // part[i][blk][k] = sum over this block's chunk of entries of conj(X_i) y, for the vectors
 // X_i = X + i * xstride (i = blockIdx.y) and every right-hand side k
 template <typename TX>
-__global__ void __launch_bounds__(DTHR) k_gm_dots(GmArgs a, const TX *X, long xstride, const float *y)
+__global__ void __launch_bounds__(DTHR) k_gm_dots(GmArgs a, const TX *X, long xstride, const float *y, int gated)
 {
     __shared__ Z red[DROWS][32];
+    if (gated && !gm_running(a)) return;
     const int G = gridDim.x, i = blockIdx.y;
     const int k = threadIdx.x & 31, row = threadIdx.x >> 5;
     const long chunk = (a.dim + G - 1) / G, e0 = blockIdx.x * chunk, e1 = e0 + chunk < a.dim ? e0 + chunk : a.dim;
@@ -150,6 +162,7 @@ constexpr int FR = 16;  // threads per inner product in k_gm_finish
 //   GM_START  : (X = y = b) the start of the iteration with ||b||^2
 __global__ void __launch_bounds__(256) k_gm_finish(GmArgs a, int G, int nvec, int col, int step)
 {
+    if (step != GM_START && !gm_running(a)) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int o = t / FR, r = t - o * FR;
     const bool ok = o < nvec * a.ldc;
@@ -193,6 +206,7 @@ int gm_blocks(const GmArgs &a, int nvec)
 // w -= sum_i hcur[k][i] V_i   (i < nvec)
 template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
 {
+    if (!gm_running(a)) return;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.dim * a.ldc) return;
     const long e = t / a.ldc;
@@ -212,8 +226,10 @@ template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs 
 }
 
 // V_dst = src * scale[k] (rounded to the basis type); dst32 (nullable): the same values as FP32
-template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, TV *dst, float *dst32)
+template <typename TV>
+__global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, TV *dst, float *dst32, int gated)
 {
+    if (gated && !gm_running(a)) return;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.dim * a.ldc) return;
     const long e = t / a.ldc;
@@ -439,15 +455,17 @@ int gmres_run(GmArgs &a, const float *b, float *u, int m, double *res_out, int32
     auto dots = [&](auto X, long xstride, int nvec, const float *y, int col, int step) {
         using TX = std::remove_const_t<std::remove_pointer_t<decltype(X)>>;
         const int G = gm_blocks(a, nvec);
-        hipLaunchKernelGGL(k_gm_dots<TX>, dim3(G, nvec), dim3(DTHR), 0, st, a, X, xstride, y);
+        hipLaunchKernelGGL(k_gm_dots<TX>, dim3(G, nvec), dim3(DTHR), 0, st, a, X, xstride, y, step != GM_START ? 1 : 0);
         if (int rc = hip_check(hipGetLastError(), "k_gm_dots launch")) return rc;
         hipLaunchKernelGGL(k_gm_finish, dim3((nvec * a.ldc * FR + 255) / 256), dim3(256), 0, st, a, G, nvec, col, step);
         return hip_check(hipGetLastError(), "k_gm_finish launch");
     };
     // beta, V_0
     if (int rc = dots(b, 0L, 1, b, 0, GM_START)) return rc;
-    hipLaunchKernelGGL(k_gm_scale<TV>, dim3(eb), dim3(GTHR), 0, st, a, b, V, a.v32);
+    hipLaunchKernelGGL(k_gm_scale<TV>, dim3(eb), dim3(GTHR), 0, st, a, b, V, a.v32, 0);
     GM_CHECK("k_gm_scale launch");
+    // every launch of an iteration (the operator's included) returns at once when no
+    // right-hand side iterates any more
     for (int j = 0; j < m; ++j) {
         // the operator's input: the basis vector itself, or its FP32 copy for a binary16 basis
         const float *vj = a.v32 ? a.v32 : (const float *)(V + (long)j * a.cvlen);
@@ -459,7 +477,7 @@ int gmres_run(GmArgs &a, const float *b, float *u, int m, double *res_out, int32
         }
         if (int rc = dots((const float *)a.w, 0L, 1, a.w, j, GM_NORM)) return rc;
         hipLaunchKernelGGL(k_gm_scale<TV>, dim3(eb), dim3(GTHR), 0, st, a, (const float *)a.w, V + (long)(j + 1) * a.cvlen,
-                           a.v32);
+                           a.v32, 1);
         GM_CHECK("k_gm_scale launch");
     }
     hipLaunchKernelGGL(k_gm_solve, dim3(kb), dim3(64), 0, st, a, res_out, iters_out);
@@ -485,7 +503,9 @@ int launch_coarse_solve(const mrhs_op *op, const float *Dc, int n_tv, const floa
     GmArgs a{};
     gm_layout(op, n_tv, n, m, (char *)ws, &a);
     a.tol = tol;
-    auto apply = [&](const float *in, float *out) { return launch_coarse_apply(op, Dc, n_tv, in, out, n, st); };
+    auto apply = [&](const float *in, float *out) {
+        return launch_coarse_apply_ex(op, Dc, 9, n_tv, nullptr, in, in, 1.f, -1, false, out, n, st, a.active, n);
+    };
     return gmres_run<float>(a, b, u, m, res_out, iters_out, apply, st);
 }
 
@@ -500,7 +520,9 @@ int launch_coarse_solve_f16(const mrhs_op *op, const __half *Dc16, int n_tv, con
     GmArgs a{};
     gm_layout(op, n_tv, n, m, (char *)ws, &a, 2);
     a.tol = tol;
-    auto apply = [&](const float *in, float *out) { return launch_coarse_apply_f16(op, Dc16, n_tv, in, out, n, st); };
+    auto apply = [&](const float *in, float *out) {
+        return launch_coarse_apply_f16(op, Dc16, n_tv, in, out, n, st, a.active, n);
+    };
     return gmres_run<__half>(a, b, u, m, res_out, iters_out, apply, st);
 }
 
@@ -554,15 +576,17 @@ int launch_coarse_solve_eo(const mrhs_op *op, const float *Dc, const float *Dinv
     const size_t cb = cvec_bytes(op, n_tv, n);
     float *bh = (float *)((char *)ws + gmb), *t1 = (float *)((char *)ws + gmb + cb), *t2 = (float *)((char *)ws + gmb + 2 * cb);
     auto ap = [&](const float *D, int nblk, const float *y0, const float *ys, const float *yh, float sh, int par, bool zero,
-                  float *out) { return launch_coarse_apply_ex(op, D, nblk, n_tv, y0, ys, yh, sh, par, zero, out, n, st); };
+                  float *out, const int *gate = nullptr) {
+        return launch_coarse_apply_ex(op, D, nblk, n_tv, y0, ys, yh, sh, par, zero, out, n, st, gate, gate ? n : 0);
+    };
     // bhat = b - H (A_oo^-1 b_o) on the even sites, 0 on the odd ones
     if (int rc = ap(Dinv, 1, nullptr, b, nullptr, 1.f, 1, true, t1)) return rc;
     if (int rc = ap(Dc, 9, b, nullptr, t1, -1.f, 0, true, bh)) return rc;
     // S v = A v - H (A_oo^-1 (H v)_o) on the even sites
     auto schur = [&](const float *in, float *out) {
-        if (int rc = ap(Dc, 9, nullptr, nullptr, in, 1.f, 1, true, t1)) return rc;
-        if (int rc = ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, true, t2)) return rc;
-        return ap(Dc, 9, nullptr, in, t2, -1.f, 0, true, out);
+        if (int rc = ap(Dc, 9, nullptr, nullptr, in, 1.f, 1, true, t1, a.active)) return rc;
+        if (int rc = ap(Dinv, 1, nullptr, t1, nullptr, 1.f, 1, true, t2, a.active)) return rc;
+        return ap(Dc, 9, nullptr, in, t2, -1.f, 0, true, out, a.active);
     };
     if (int rc = gmres_run<float>(a, bh, u, m, res_out, iters_out, schur, st)) return rc;
     // u_o = A_oo^-1 (b - H u)_o, the even sites of u kept

@@ -38,12 +38,13 @@ int launch_coarse_apply(const mrhs_op *op, const float *Dc, int n_tv, const floa
 // the general form: yco = y0 + D_self yself + s_hop * sum_d D_d yhop(nbr_d) with D = Dc[site][0..nblk),
 // on every coarse site (parity -1) or those of one parity (the others zeroed or left untouched);
 // null inputs drop their terms
+// gate (nullable, gate_n flags): the launch does nothing when every flag is zero
 int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
                            const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
-                           hipStream_t st);
+                           hipStream_t st, const int *gate = nullptr, int gate_n = 0);
 // yco = D_c yc with D_c stored in binary16 (as written by launch_coarse with MRHS_DTYPE_F16)
 int launch_coarse_apply_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *yc, float *yco, int n,
-                            hipStream_t st);
+                            hipStream_t st, const int *gate = nullptr, int gate_n = 0);
 size_t transfer_lds_bytes(const mrhs_op *op);
 // even-odd preconditioned coarse solve and the self-block inverses it uses
 size_t ws_bytes_coarse_solve_eo(const mrhs_op *op, int n_tv, int n, int m);

@@ -259,7 +259,18 @@ struct CApplyArgs {
     int parity;          // -1: every coarse site; 0 / 1: only the sites of that parity
     int zero_other;      // the other sites' output: 1 written as zero, 0 left untouched
     float *yco;
+    const int *gate;     // nullable: with every one of its gate_n flags zero the launch does nothing
+    int gate_n;
 };
+
+// uniform over the grid: false when a gate is given and all its flags are zero
+__device__ inline bool apply_gate_open(const CApplyArgs &a)
+{
+    if (!a.gate) return true;
+    bool any = false;
+    for (int k = 0; k < a.gate_n; ++k) any |= a.gate[k] != 0;
+    return any;
+}
 
 constexpr int CA_GROUPS = 3;
 #ifndef CA_SITE_MIN
@@ -271,6 +282,7 @@ template <int KS> __global__ void __launch_bounds__(CA_MAXTHR) k_coarse_apply(CA
 {
     __shared__ f4 part[CA_GROUPS - 1][2][2][64];  // [g - 1][tk][re, im][lane]
     __shared__ float slab[CA_GROUPS][16 * 130];  // 16 rows of 2N complex, row stride 4N + 2 floats
+    if (!apply_gate_open(a)) return;
     const int N2 = 2 * a.N, TR = (N2 + 15) / 16, TK = (a.n + 15) / 16, RS = 2 * N2 + 2;
     const int i = blockIdx.x / TR, tr = blockIdx.x - i * TR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -418,6 +430,7 @@ template <> struct SlabLoad<__half> {
 template <typename TD, int QN, int TK> __global__ void __launch_bounds__(256) k_coarse_apply_site(CApplyArgs a)
 {
     __shared__ float2 ys[2][CS_ROWS * CS_YRS];
+    if (!apply_gate_open(a)) return;
     using SL = SlabLoad<TD>;
     const int N2 = 2 * a.N, nthr = blockDim.x;
     const int i = xcd_remap(blockIdx.x, a.Vc);
@@ -676,9 +689,11 @@ namespace {
 
 int coarse_apply_any(const mrhs_op *op, const float *Dc, const __half *Dc16, int nblk, int n_tv, const float *y0,
                      const float *yself, const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
-                     hipStream_t st)
+                     hipStream_t st, const int *gate, int gate_n)
 {
     CApplyArgs a{};
+    a.gate = gate;
+    a.gate_n = gate_n;
     a.Dc16 = Dc16;
     for (int mu = 0; mu < 4; ++mu) a.na[mu] = op->na[mu];
     a.Vc = op->n_agg;
@@ -708,13 +723,14 @@ int coarse_apply_any(const mrhs_op *op, const float *Dc, const __half *Dc16, int
 
 int launch_coarse_apply_ex(const mrhs_op *op, const float *Dc, int nblk, int n_tv, const float *y0, const float *yself,
                            const float *yhop, float s_hop, int parity, bool zero_other, float *yco, int n,
-                           hipStream_t st)
+                           hipStream_t st, const int *gate, int gate_n)
 {
-    return coarse_apply_any(op, Dc, nullptr, nblk, n_tv, y0, yself, yhop, s_hop, parity, zero_other, yco, n, st);
+    return coarse_apply_any(op, Dc, nullptr, nblk, n_tv, y0, yself, yhop, s_hop, parity, zero_other, yco, n, st, gate,
+                            gate_n);
 }
 
 int launch_coarse_apply_f16(const mrhs_op *op, const __half *Dc16, int n_tv, const float *yc, float *yco, int n,
-                            hipStream_t st)
+                            hipStream_t st, const int *gate, int gate_n)
 {
-    return coarse_apply_any(op, nullptr, Dc16, 9, n_tv, nullptr, yc, yc, 1.f, -1, false, yco, n, st);
+    return coarse_apply_any(op, nullptr, Dc16, 9, n_tv, nullptr, yc, yc, 1.f, -1, false, yco, n, st, gate, gate_n);
 }
