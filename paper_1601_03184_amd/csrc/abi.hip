@@ -67,15 +67,16 @@ size_t sap_lds_bytes(const mrhs_op *op, int T)
     return esz * (24 * (size_t)op->k.Vb * T + threads / 64 * T * 3);
 }
 
-// SAP tiles with FP64 arithmetic above 2 right-hand sides per site need more registers
-// than a workgroup of that size may hold (the kernels would spill to scratch)
-bool sap_tile_built(const mrhs_op *op, int T) { return op->prec != MRHS_PREC_F64 || T <= 2; }
+// SAP and stencil tiles with FP64 arithmetic above 2 right-hand sides per site need more
+// registers than a workgroup of that size may hold (the kernels would spill to scratch):
+// they are not built
+bool tile_built(const mrhs_op *op, int T) { return op->prec != MRHS_PREC_F64 || T <= 2; }
 
 int pick_tile(const mrhs_op *op, int want, bool sap)
 {
     int t = want;
-    while (t > 1 && (op->k.S % t != 0 || op->k.Vb * t > 1024 ||
-                     (sap && (sap_lds_bytes(op, t) > op->max_lds || !sap_tile_built(op, t)))))
+    while (t > 1 && (op->k.S % t != 0 || op->k.Vb * t > 1024 || !tile_built(op, t) ||
+                     (sap && sap_lds_bytes(op, t) > op->max_lds)))
         t >>= 1;
     return t;
 }
@@ -625,13 +626,15 @@ int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile)
             return set_error(MRHS_EINVAL, "SAP tile must be 1, 2 or 4, divide S and fit the block");
         if (sap_lds_bytes(op, sap_tile) > op->max_lds)
             return set_error(MRHS_EUNSUPPORTED, "SAP tile exceeds the LDS of a workgroup");
-        if (!sap_tile_built(op, sap_tile))
+        if (!tile_built(op, sap_tile))
             return set_error(MRHS_EUNSUPPORTED, "SAP tiles above 2 are not built for FP64 arithmetic");
         op->sap_tile = sap_tile;
     }
     if (dirac_tile) {
         if (!ok(dirac_tile) || op->k.S % dirac_tile || op->k.Vb * dirac_tile > 1024)
             return set_error(MRHS_EINVAL, "stencil tile must be 1, 2 or 4, divide S and fit the block");
+        if (!tile_built(op, dirac_tile))
+            return set_error(MRHS_EUNSUPPORTED, "stencil tiles above 2 are not built for FP64 arithmetic");
         op->dirac_tile = dirac_tile;
     }
     return MRHS_OK;

@@ -146,9 +146,13 @@ int dirac_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const v
                            (const Ts *)x, (Ts *)y, ntiles);
         break;
     case 4:
-        hipLaunchKernelGGL((k_dirac<Ts, Tc, 4>), grid, block, 0, st, g, links, clover, op->blk_coords, op->loc_coords,
-                           (const Ts *)x, (Ts *)y, ntiles);
-        break;
+        // tile 4 only with FP32 arithmetic (FP64 would spill to scratch)
+        if constexpr (sizeof(Tc) == 4) {
+            hipLaunchKernelGGL((k_dirac<Ts, Tc, 4>), grid, block, 0, st, g, links, clover, op->blk_coords,
+                               op->loc_coords, (const Ts *)x, (Ts *)y, ntiles);
+            break;
+        }
+        return set_error(MRHS_EUNSUPPORTED, "dirac tile not built");
     default:
         return set_error(MRHS_EUNSUPPORTED, "dirac tile not built");
     }

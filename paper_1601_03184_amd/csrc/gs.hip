@@ -340,7 +340,9 @@ __device__ inline void stage_sites(const GsArgs &a, int i, int ls0, int n, uint3
 // One workgroup per (aggregate i, half h).  Every pass walks the rows in 16-row blocks,
 // NW blocks apart per wavefront, with the next block's elements loaded while the current
 // one is on the matrix cores.
-template <typename Tv, typename Tq, int NT> __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
+// three workgroups per CU (168 VGPRs) where the FP32 or binary16 input allows it without spilling
+template <typename Tv, typename Tq, int NT>
+__global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;

@@ -120,6 +120,13 @@ def test_abi_rejects_bad_arguments():
     with pytest.raises(mrhs.MrhsError) as e:
         mrhs.mrhs_set_tiles(op.handle, 3, 0)
     assert e.value.code == mrhs.MRHS_EINVAL
+    # FP64 tiles above 2 are not built (they would spill): refused, the op keeps its tiles
+    op64 = case.op([2, 2, 2, 2], prec=F64, short_len=4)
+    for sap_tile, dirac_tile in ((4, 0), (0, 4)):
+        with pytest.raises(mrhs.MrhsError) as e:
+            mrhs.mrhs_set_tiles(op64.handle, sap_tile, dirac_tile)
+        assert e.value.code == mrhs.MRHS_EUNSUPPORTED
+    op64.close()
     with pytest.raises(mrhs.MrhsError) as e:
         mrhs.Operator([4, 4, 4, 6], [2, 2, 2, 4], [2, 2, 2, 2], torch.from_numpy(inputs.gauge_field([4, 4, 4, 6], 0.3, 1)),
                       0.0, 1.0)
