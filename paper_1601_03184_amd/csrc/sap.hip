@@ -214,6 +214,11 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     const int colour = a.colour, mode = a.mode;
     const uint32_t *bcs = a.blk_coords;
     auto skip = [=](int nblk) { return mode == 1 && block_colour(g, bcs, nblk) == colour; };
+    // The face hops F of this visit (what the other blocks' x contribute) are what sigma for the
+    // next visit needs as well (sigma' = rho + F, step 4): where step 1 forms them on their own
+    // (a sigma visit, or the first visit of the second colour, where x vanishes on the block so
+    // that D x is F), they are kept in this site's sigma slot until step 4.
+    const bool keep_f = a.sig_out && (a.sig_in || a.mode == 1);
     if (active) {
         Spinor<Tc> r;
         if (a.mode != 0) {
@@ -226,6 +231,7 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
                 dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
                 load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
             }
+            if (keep_f) store_spinor(g, a.sig, grp, blk, off, tt, r);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 r.re[c] = bb.re[c] - r.re[c];
@@ -339,9 +345,12 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     }
     // 4. sigma for the next visit: b - D_j x_j(new) = rho (the block residual after the MR
     //    steps, this lane's own LDS slot) + the face hops, which this half-sweep leaves unchanged
+    //    (kept from step 1, or formed again after a full residual)
     if (active && a.sig_out) {
         Spinor<Tc> sg;
-        if (a.mode != 0) {
+        if (keep_f) {
+            load_spinor<Tc>(g, a.sig, grp, blk, off, tt, sg);
+        } else if (a.mode != 0) {
             // the coordinates are decoded again rather than kept live through the MR steps
             int bc2[4], lc2[4];
             decode_site(g, a.blk_coords, a.loc_coords, blk, opaque_index(off), bc2, lc2);
