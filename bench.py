@@ -85,18 +85,29 @@ def log(msg):
 
 
 def sap_flops_per_call(V, n, n_sap, n_mr, block):
-    """Arithmetic the SAP call needs: block-operator MR steps on every site, the residual
-    (skipped where x is still zero: the first red half-sweep, and same-colour blocks in the
-    first black half-sweep)."""
+    """Arithmetic the SAP call performs: the block-operator MR steps on every site; the
+    residual where x is not known to vanish, which is only the hops across block faces (in the
+    first black half-sweep x vanishes on the block itself; at every later visit sigma =
+    b_j - D_j x_j is kept from the previous one); and sigma' = rho + F where sigma is kept
+    for a later visit (a copy of rho in the first red half-sweep)."""
     Vb = int(np.prod(block))
     inner = sum((Vb - Vb // b) for b in block) * 2 / (8.0 * Vb)   # fraction of hops inside a block
     hop = 1320.0
     rest = pm.STENCIL_FLOP - hop
     mr = n_mr * (rest + hop * inner + pm.MR_EXTRA_FLOP)
-    full_res = pm.STENCIL_FLOP + pm.RESIDUAL_EXTRA_FLOP
-    first_black_res = hop * (1 - inner) + pm.RESIDUAL_EXTRA_FLOP
+    face_res = hop * (1 - inner) + pm.RESIDUAL_EXTRA_FLOP
+    sigma_update = pm.RESIDUAL_EXTRA_FLOP
     half = V / 2.0 * n
-    return half * mr + half * (mr + first_black_res) + (n_sap - 1) * 2 * half * (mr + full_res)
+    total = 0.0
+    for sweep in range(n_sap):
+        for c in range(2):
+            t = mr
+            if sweep > 0 or c == 1:
+                t += face_res
+                if sweep + 1 < n_sap:
+                    t += sigma_update
+            total += half * t
+    return total
 
 
 def sap_bytes_per_call(V, n, n_sap, store_b, field_b):
