@@ -110,22 +110,28 @@ def sap_flops_per_call(V, n, n_sap, n_mr, block):
     return total
 
 
-def sap_bytes_per_call(V, n, n_sap, store_b, field_b):
+def sap_bytes_per_call(V, n, n_sap, store_b, field_b, sigma_b=4):
     """Algorithmic HBM bytes of a SAP call: per half-sweep the fields of that colour's sites
-    once, b and x of those sites (x read except in the first sweep), x written, and the
-    x of the other colour that the residual reads, counted once per site."""
+    once; in the first sweep b read, in later ones the kept sigma (arithmetic type) and the own
+    x read; x written; the x of the other colour that the residual reads, counted once per
+    site; sigma written where a later visit needs it."""
     half = V // 2
     s = pm.SPINOR_REALS * store_b
+    sg = pm.SPINOR_REALS * sigma_b
     f = (4 * pm.LINK_REALS + pm.CLOVER_REALS) * field_b
     total = 0.0
     for sweep in range(n_sap):
         for c in range(2):
             total += half * f
-            total += half * n * s * 2                     # b read, x written
-            if sweep > 0:
-                total += half * n * s                     # x read (own)
+            total += half * n * s                         # x written
+            if sweep == 0:
+                total += half * n * s                     # b read
+            else:
+                total += half * n * (sg + s)              # sigma and the own x read
             if sweep > 0 or c == 1:
                 total += half * n * s                     # halo x of the other colour
+            if sweep + 1 < n_sap:
+                total += half * n * sg                    # sigma written
     return total
 
 
