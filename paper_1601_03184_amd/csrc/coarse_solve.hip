@@ -53,10 +53,26 @@ struct GmArgs {
 // right-hand side has stopped
 __device__ inline bool gm_running(const GmArgs &a)
 {
-    bool any = false;
-    for (int k = 0; k < a.n; ++k) any |= a.active[k] != 0;
-    return any;
+    // one flag per lane (at most 32 right-hand sides), combined over the wavefront; called
+    // first thing, with every lane of the wavefront active
+    const int l = threadIdx.x & 63;
+    const int f = l < a.n ? a.active[l] : 0;
+    return __ballot(f != 0) != 0;
 }
+
+// element of thread t of an elementwise launch: entry e = t / ldc, right-hand side k; its real
+// part at cre(e, k) (a coarse vector has fewer than 2^31 floats, checked on the host)
+__device__ inline bool gm_elem(const GmArgs &a, uint32_t &o, int &k)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x, ldc = (uint32_t)a.ldc;
+    if (t >= (uint32_t)a.dim * ldc) return false;
+    const uint32_t e = t / ldc;
+    k = (int)(t - e * ldc);
+    o = 2 * e * ldc + (uint32_t)k;
+    return true;
+}
+
+constexpr int GU = 8;  // basis vectors whose loads an elementwise kernel issues together
 
 // element (e, k) of a coarse vector: entry e = site * 2 n_tv + dof, right-hand side k
 __device__ inline long cre(const GmArgs &a, long e, int k) { return (2 * e) * a.ldc + k; }
@@ -207,19 +223,27 @@ int gm_blocks(const GmArgs &a, int nvec)
 template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_axpy(GmArgs a, int nvec)
 {
     if (!gm_running(a)) return;
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.dim * a.ldc) return;
-    const long e = t / a.ldc;
-    const int k = (int)(t - e * a.ldc);
-    const long o = cre(a, e, k);
+    uint32_t o;
+    int k;
+    if (!gm_elem(a, o, k)) return;
     double wr = a.w[o], wi = a.w[o + a.ldc];
-    for (int i = 0; i < nvec; ++i) {
-        const Z h = a.hcur[(long)k * (a.m + 1) + i];
-        const TV *vi = (const TV *)a.V + i * a.cvlen;
-        const Z v = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
-        const Z p = zmul(h, v);
-        wr -= p.re;
-        wi -= p.im;
+    for (int i0 = 0; i0 < nvec; i0 += GU) {
+        Z h[GU], v[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            h[u] = v[u] = {0.0, 0.0};
+            if (i0 + u < nvec) {
+                const TV *vi = (const TV *)a.V + (long)(i0 + u) * a.cvlen;
+                h[u] = a.hcur[(long)k * (a.m + 1) + i0 + u];
+                v[u] = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const Z p = zmul(h[u], v[u]);
+            wr -= p.re;
+            wi -= p.im;
+        }
     }
     a.w[o] = (float)wr;
     a.w[o + a.ldc] = (float)wi;
@@ -230,11 +254,9 @@ template <typename TV>
 __global__ void __launch_bounds__(GTHR) k_gm_scale(GmArgs a, const float *src, TV *dst, float *dst32, int gated)
 {
     if (gated && !gm_running(a)) return;
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.dim * a.ldc) return;
-    const long e = t / a.ldc;
-    const int k = (int)(t - e * a.ldc);
-    const long o = cre(a, e, k);
+    uint32_t o;
+    int k;
+    if (!gm_elem(a, o, k)) return;
     const double s = a.scale[k];
     const TV re = store_as<TV>((float)(src[o] * s)), im = store_as<TV>((float)(src[o + a.ldc] * s));
     dst[o] = re;
@@ -275,20 +297,28 @@ __global__ void k_gm_solve(GmArgs a, double *res_out, int32_t *iters_out)
 // u = sum_i y_i V_i
 template <typename TV> __global__ void __launch_bounds__(GTHR) k_gm_combine(GmArgs a, float *u)
 {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.dim * a.ldc) return;
-    const long e = t / a.ldc;
-    const int k = (int)(t - e * a.ldc);
-    const long o = cre(a, e, k);
+    uint32_t o;
+    int k;
+    if (!gm_elem(a, o, k)) return;
     double ur = 0.0, ui = 0.0;
     const int J = a.J[k];
-    for (int i = 0; i < J; ++i) {
-        const Z y = a.hcur[(long)k * (a.m + 1) + i];
-        const TV *vi = (const TV *)a.V + i * a.cvlen;
-        const Z v = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
-        const Z p = zmul(y, v);
-        ur += p.re;
-        ui += p.im;
+    for (int i0 = 0; i0 < J; i0 += GU) {
+        Z y[GU], v[GU];
+#pragma unroll
+        for (int q = 0; q < GU; ++q) {
+            y[q] = v[q] = {0.0, 0.0};
+            if (i0 + q < J) {
+                const TV *vi = (const TV *)a.V + (long)(i0 + q) * a.cvlen;
+                y[q] = a.hcur[(long)k * (a.m + 1) + i0 + q];
+                v[q] = {load_as<double>(vi + o), load_as<double>(vi + o + a.ldc)};
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < GU; ++q) {
+            const Z p = zmul(y[q], v[q]);
+            ur += p.re;
+            ui += p.im;
+        }
     }
     u[o] = k < a.n ? (float)ur : 0.f;
     u[o + a.ldc] = k < a.n ? (float)ui : 0.f;
@@ -447,6 +477,7 @@ int gmres_run(GmArgs &a, const float *b, float *u, int m, double *res_out, int32
               hipStream_t st)
 {
     const long nel = a.dim * a.ldc;
+    if (a.cvlen >= (1L << 31)) return set_error(MRHS_EUNSUPPORTED, "coarse solve: a coarse vector above 2^31 floats");
     const int eb = (int)((nel + GTHR - 1) / GTHR);
     const int kb = (a.ldc + 63) / 64;
     TV *V = (TV *)a.V;

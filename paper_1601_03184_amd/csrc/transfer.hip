@@ -263,13 +263,14 @@ struct CApplyArgs {
     int gate_n;
 };
 
-// uniform over the grid: false when a gate is given and all its flags are zero
+// uniform over the grid: false when a gate is given and all its flags are zero (at most 32
+// flags, one per lane, combined over the wavefront; called with every lane active)
 __device__ inline bool apply_gate_open(const CApplyArgs &a)
 {
     if (!a.gate) return true;
-    bool any = false;
-    for (int k = 0; k < a.gate_n; ++k) any |= a.gate[k] != 0;
-    return any;
+    const int l = threadIdx.x & 63;
+    const int f = l < a.gate_n ? a.gate[l] : 0;
+    return __ballot(f != 0) != 0;
 }
 
 constexpr int CA_GROUPS = 3;
