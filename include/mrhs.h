@@ -119,17 +119,20 @@ int dirac_apply_mrhs(const mrhs_op *op, const void *x, void *y, int32_t n_rhs, v
  * b - D x is formed on that colour's blocks, then every block j adds n_mr minimal-
  * residual steps on D_j = I_j^T D I_j (step length 0 when <q,q> = 0).  b, x: native
  * vectors of the op's element type, x != b; x is overwritten.  ws: workspace of at
- * least mrhs_workspace_bytes(op, n_rhs) bytes: with the plain MR block solver it carries
- * sigma_j = b_j - D_j x_j (arithmetic type, one vector set) from one visit of a block to
- * the next, so that a later residual is sigma_j minus the hops across the block's faces
- * (the same residual up to rounding order); a snapshot of x when a direction holds an odd
- * number of blocks. */
+ * least mrhs_workspace_bytes(op, n_rhs) bytes.  With the plain MR block solver it carries
+ * a block's residual from one visit to the next, so that a later visit forms only the hops
+ * across the block's faces (the same residual up to rounding order): when no direction holds
+ * an odd number (> 1) of blocks, the block residual rho_j after its MR steps and every block's
+ * last change of x (arithmetic type, one vector set each), a later residual being rho_j minus
+ * the face hops of the neighbours' changes; otherwise sigma_j = b_j - D_j x_j and a snapshot
+ * of x, a later residual being sigma_j minus the face hops of x. */
 int sap_smooth_mrhs(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
                     void *ws, size_t ws_bytes, void *stream);
 
 /* As sap_smooth_mrhs, but x holds the starting guess on entry (the refinement phase of the
- * setup, Alg. 1 and 2: the smoother starts from the prolongated coarse-grid solution); every
- * half-sweep forms the full residual.  With n_sap = 0, x is left as it is. */
+ * setup, Alg. 1 and 2: the smoother starts from the prolongated coarse-grid solution); the
+ * first visit of each colour forms the full residual b - D x.  With n_sap = 0, x is left as
+ * it is. */
 int sap_smooth_mrhs_guess(const mrhs_op *op, const void *b, void *x, int32_t n_rhs, int32_t n_sap, int32_t n_mr,
                           void *ws, size_t ws_bytes, void *stream);
 

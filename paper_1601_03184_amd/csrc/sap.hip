@@ -39,6 +39,13 @@ template <typename Ts, typename Tc> struct SapArgs {
     Tc *sig;
     int sig_in;             // this colour's sigma is valid (read it instead of forming b - D x)
     int sig_out;            // write sigma for the next visit of this colour
+    // incremental residual (no block has a neighbour of its own colour): sig holds the block's
+    // residual rho after its last visit, ecor each block's last change of x; a later visit's
+    // residual is rho - (face hops of the neighbours' changes since then), the change the
+    // other colour made in between
+    int inc;
+    Tc *ecor;
+    int e_out;              // write this visit's change of x (a later visit reads it)
     // even-odd block solver: A^-1 per site (clover layout), block offsets in parity order,
     // number of even sites of a block
     const Tc *cloverinv;
@@ -218,14 +225,15 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
     // next visit needs as well (sigma' = rho + F, step 4): where step 1 forms them on their own
     // (a sigma visit, or the first visit of the second colour, where x vanishes on the block so
     // that D x is F), they are kept in this site's sigma slot until step 4.
-    const bool keep_f = a.sig_out && (a.sig_in || a.mode == 1);
+    const bool keep_f = !a.inc && a.sig_out && (a.sig_in || a.mode == 1);
     if (active) {
         Spinor<Tc> r;
         if (a.mode != 0) {
             Spinor<Tc> bb;
             if (a.sig_in) {
                 spinor_zero(r);
-                face_hops_global<Tc>(g, a.links, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+                if (a.inc) face_hops_global<Tc>(g, a.links, (const Tc *)a.ecor, grp, tt, blk, off, bc, lc, r, skip);
+                else face_hops_global<Tc>(g, a.links, a.xr, grp, tt, blk, off, bc, lc, r, skip);
                 load_spinor<Tc>(g, a.sig, grp, blk, off, tt, bb);
             } else {
                 dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
@@ -330,10 +338,11 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
         }
     }
 
-    // 3. x|_j (+)= e
+    // 3. x|_j (+)= e; with the incremental residual also the change of the stored x (the
+    //    correction as rounded to the storage type)
     if (active) {
+        Spinor<Tc> xo;
         if (a.mode == 2) {
-            Spinor<Tc> xo;
             load_spinor<Tc>(g, a.x, grp, blk, off, tt, xo);
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
@@ -342,11 +351,29 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
             }
         }
         store_spinor(g, a.x, grp, blk, off, tt, e);
+        if (a.e_out) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                Ts sr = store_as<Ts>(e.re[c]), si = store_as<Ts>(e.im[c]);
+                e.re[c] = load_as<Tc>(&sr);
+                e.im[c] = load_as<Tc>(&si);
+                if (a.mode == 2) {
+                    e.re[c] -= xo.re[c];
+                    e.im[c] -= xo.im[c];
+                }
+            }
+            store_spinor(g, a.ecor, grp, blk, off, tt, e);
+        }
     }
     // 4. sigma for the next visit: b - D_j x_j(new) = rho (the block residual after the MR
     //    steps, this lane's own LDS slot) + the face hops, which this half-sweep leaves unchanged
     //    (kept from step 1, or formed again after a full residual)
-    if (active && a.sig_out) {
+    if (active && a.sig_out && a.inc) {
+        // the incremental residual keeps rho itself
+        Spinor<Tc> rr;
+        lds_load<Tc>(rho, str, me, rr);
+        store_spinor(g, a.sig, grp, blk, off, tt, rr);
+    } else if (active && a.sig_out) {
         Spinor<Tc> sg;
         if (keep_f) {
             load_spinor<Tc>(g, a.sig, grp, blk, off, tt, sg);
@@ -779,6 +806,11 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
         }
         a.sig = (Tc *)wp;
         wp += align256(native_elems(op, n_rhs[k]) * sizeof(Tc));
+        a.ecor = nullptr;
+        if (!op->odd_blocks) {
+            a.ecor = (Tc *)wp;
+            wp += align256(native_elems(op, n_rhs[k]) * sizeof(Tc));
+        }
     }
     for (int s = 0; s < n_sap; ++s)
         for (int c = 0; c < 2; ++c) {
@@ -794,6 +826,10 @@ int sap_batched_dispatch(const mrhs_op *const *ops, int n, const void *const *b,
                 // sigma carries a colour's residual from one visit to the next (plain MR only)
                 a.sig_in = !eo && s > 0;
                 a.sig_out = !eo && s + 1 < n_sap;
+                // the incremental residual where no block neighbours one of its own colour: every
+                // visit but the call's last one leaves its change of x for the other colour
+                a.inc = !eo && !op->odd_blocks;
+                a.e_out = a.inc && !(s + 1 == n_sap && c == 1);
                 a.xr = a.x;
                 if (a.mode == 2 && op->odd_blocks) {
                     C.src[C.n_inst] = a.x;
@@ -840,8 +876,10 @@ size_t ws_bytes_sap_batched(const mrhs_op *const *ops, int n, const int32_t *n_r
     size_t w = 0;
     for (int k = 0; k < n; ++k) {
         const size_t ne = native_elems(ops[k], n_rhs[k]);
-        if (ops[k]->odd_blocks) w += align256(ne * dtype_size(ops[k]->dtype));
-        w += align256(ne * (ops[k]->prec == MRHS_PREC_F64 ? sizeof(double) : sizeof(float)));  // sigma
+        const size_t tc = ops[k]->prec == MRHS_PREC_F64 ? sizeof(double) : sizeof(float);
+        if (ops[k]->odd_blocks) w += align256(ne * dtype_size(ops[k]->dtype));  // snapshot of x
+        else w += align256(ne * tc);                                             // changes of x
+        w += align256(ne * tc);                                                  // sigma / rho
     }
     return w;
 }
