@@ -56,7 +56,7 @@ TOL = {"f32": 1e-5, "f16_storage": 5e-3, "f64": 1e-12}
 SAP_SOURCES = ["paper_1601_03184_amd/csrc/sap.hip", "paper_1601_03184_amd/csrc/stencil.h",
                "paper_1601_03184_amd/csrc/internal.h"]
 SAP_TRAFFIC = {"sources_sha1": "e76bfd00dd6642e5530a4175150e99dc7f3d37d1", "fetch_scale": 2.0, "write_scale": 1.0,
-               "kib": {4: (42413933, 34504493)}}
+               "kib": {}}
 
 
 def sources_sha1():
@@ -85,36 +85,31 @@ def log(msg):
 
 
 def sap_flops_per_call(V, n, n_sap, n_mr, block):
-    """Arithmetic the SAP call performs: the block-operator MR steps on every site; the
+    """Arithmetic the SAP call performs: the block-operator MR steps on every site, and the
     residual where x is not known to vanish, which is only the hops across block faces (in the
-    first black half-sweep x vanishes on the block itself; at every later visit sigma =
-    b_j - D_j x_j is kept from the previous one); and sigma' = rho + F where sigma is kept
-    for a later visit (a copy of rho in the first red half-sweep)."""
+    first black half-sweep x vanishes on the block itself; at every later visit the block's
+    residual is kept from its previous one and the face hops of the neighbours' changes of x
+    are subtracted)."""
     Vb = int(np.prod(block))
     inner = sum((Vb - Vb // b) for b in block) * 2 / (8.0 * Vb)   # fraction of hops inside a block
     hop = 1320.0
     rest = pm.STENCIL_FLOP - hop
     mr = n_mr * (rest + hop * inner + pm.MR_EXTRA_FLOP)
     face_res = hop * (1 - inner) + pm.RESIDUAL_EXTRA_FLOP
-    sigma_update = pm.RESIDUAL_EXTRA_FLOP
     half = V / 2.0 * n
     total = 0.0
     for sweep in range(n_sap):
         for c in range(2):
-            t = mr
-            if sweep > 0 or c == 1:
-                t += face_res
-                if sweep + 1 < n_sap:
-                    t += sigma_update
-            total += half * t
+            total += half * (mr + (face_res if sweep > 0 or c == 1 else 0.0))
     return total
 
 
 def sap_bytes_per_call(V, n, n_sap, store_b, field_b, sigma_b=4):
     """Algorithmic HBM bytes of a SAP call: per half-sweep the fields of that colour's sites
-    once; in the first sweep b read, in later ones the kept sigma (arithmetic type) and the own
-    x read; x written; the x of the other colour that the residual reads, counted once per
-    site; sigma written where a later visit needs it."""
+    once; in the first sweep b read, in later ones the kept block residual (arithmetic type)
+    and the own x read; x written; the other colour's x (first black half-sweep) or change of x
+    (later visits) that the face hops read, counted once per site; the block residual and the
+    change of x written where a later visit reads them."""
     half = V // 2
     s = pm.SPINOR_REALS * store_b
     sg = pm.SPINOR_REALS * sigma_b
@@ -127,11 +122,15 @@ def sap_bytes_per_call(V, n, n_sap, store_b, field_b, sigma_b=4):
             if sweep == 0:
                 total += half * n * s                     # b read
             else:
-                total += half * n * (sg + s)              # sigma and the own x read
-            if sweep > 0 or c == 1:
-                total += half * n * s                     # halo x of the other colour
+                total += half * n * (sg + s)              # block residual and the own x read
+            if sweep == 0 and c == 1:
+                total += half * n * s                     # the other colour's x
+            elif sweep > 0:
+                total += half * n * sg                    # the other colour's change of x
             if sweep + 1 < n_sap:
-                total += half * n * sg                    # sigma written
+                total += half * n * sg                    # block residual written
+            if not (sweep + 1 == n_sap and c == 1):
+                total += half * n * sg                    # change of x written
     return total
 
 
