@@ -189,6 +189,51 @@ def test_coarse_gmres_parity(L, block, agg, prec, S, n_tv, n, m, tol):
     op.close()
 
 
+@pytest.mark.parametrize("f16", [False, True])
+def test_coarse_gmres_zero_rhs_and_early_stop(f16):
+    """Right-hand sides that are zero never iterate (solution 0, 0 iterations, residual 0),
+    and with a loose tolerance every other one stops after its first iteration, so the later
+    Arnoldi steps of the fixed launch sequence find no right-hand side iterating: the result
+    is still the oracle's GMRES, and the solution of a zero right-hand side is exactly zero."""
+    need_gpu()
+    L, block, agg, n_tv, n, m, tol = [8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], 20, 6, 8, 0.9
+    announce("coarse gmres zero rhs, tol %g, f16=%d" % (tol, f16))
+    case, op, qn, qin = _setup(L, block, agg, F32, 4, n_tv, D32)
+    Vc, nc = op.n_agg, 2 * n_tv
+    Dc = torch.zeros(Vc * 9 * nc * nc * 2, dtype=torch.float32, device="cuda")
+    mrhs.coarse_op_build(op.handle, qn, D32, n_tv, Dc, None)
+    D16 = Dc.half()
+    Dh = (D16 if f16 else Dc).cpu().double().numpy().view(np.complex128).reshape(Vc, 9, nc, nc)
+    rng = np.random.default_rng(336)
+    bc = rng.standard_normal((n, Vc, 2, n_tv)) + 1j * rng.standard_normal((n, Vc, 2, n_tv))
+    bc[[1, 4]] = 0
+    bc32 = (bc.real.astype(np.float32) + 1j * bc.imag.astype(np.float32)).astype(np.complex128)
+    bn = coarse_to_native(bc32, (n + 3) // 4 * 4)
+    un = op.coarse_empty(n_tv, n)
+    un.fill_(float("nan"))
+    res = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    its = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    if f16:
+        ws = torch.empty(mrhs.mrhs_coarse_solve_f16_workspace_bytes(op.handle, n_tv, n, m), dtype=torch.uint8,
+                         device="cuda")
+        mrhs.coarse_solve_f16_mrhs(op.handle, D16, n_tv, bn, un, n, m, tol, ws, res, its)
+    else:
+        ws = torch.empty(mrhs.mrhs_coarse_solve_workspace_bytes(op.handle, n_tv, n, m), dtype=torch.uint8,
+                         device="cuda")
+        mrhs.coarse_solve_mrhs(op.handle, Dc, n_tv, bn, un, n, m, tol, ws, res, its)
+    got = coarse_from_native(un, Vc, n_tv, n)
+    ref, rref, iref = oracle.coarse_gmres(L, agg, Dh, bc32, m, tol)
+    it, r = its.cpu().numpy(), res.cpu().numpy()
+    assert np.all(got[[1, 4]] == 0)
+    assert it[1] == 0 and it[4] == 0 and r[1] == 0 and r[4] == 0
+    live = [0, 2, 3, 5]
+    assert np.all(it[live] == 1), it
+    assert np.array_equal(it, iref)
+    assert per_rhs_rel(got[live], ref[live]) < (5e-3 if f16 else 1e-5)
+    assert np.all(r[live] <= tol)
+    op.close()
+
+
 EO_GMRES_CASES = [
     # (L, block, agg, prec, S, n_tv, n, m, tol): every coarse extent even
     ([8, 8, 8, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, 13, 8, 0.0),
