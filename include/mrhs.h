@@ -303,10 +303,12 @@ size_t mrhs_batched_workspace_bytes(mrhs_op *const *ops, int32_t n_inst, const i
 #define MRHS_BLOCK_EO_MR 1
 int mrhs_set_block_solver(mrhs_op *op, int32_t solver, void *stream);
 
-/* Execution tiles (right-hand sides per workgroup) of the SAP and stencil kernels; 0 keeps
- * the current choice.  A tile must divide the op's short length and fit the block
- * (EINVAL otherwise); SAP tiles above 2 with FP64 arithmetic are not built
- * (EUNSUPPORTED: they would not fit the register file). */
+/* Execution tiles (right-hand sides per site that share one workgroup's field loads) of the
+ * SAP and stencil kernels; 0 keeps the current choice.  A tile must divide the op's short
+ * length and fit the block (EINVAL otherwise); SAP and stencil tiles above 2 with FP64
+ * arithmetic are not built (EUNSUPPORTED: they would not fit the register file).  The
+ * stencil at tile 4 on a short length of 4 with FP32 arithmetic takes two groups of 4
+ * right-hand sides per workgroup.  Tiles change the execution only, never a result. */
 int mrhs_set_tiles(mrhs_op *op, int32_t sap_tile, int32_t dirac_tile);
 
 /* the op's current SAP block solver (MRHS_BLOCK_MR or MRHS_BLOCK_EO_MR) */

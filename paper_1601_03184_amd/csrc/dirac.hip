@@ -39,6 +39,31 @@ __global__ void __launch_bounds__(256 * T) k_dirac(KGeo g, const Tc *__restrict_
     store_spinor(g, y, grp, blk, off, tt, out);
 }
 
+// The stencil at tile 4 on a short length of 4 (FP32): a workgroup takes two consecutive
+// groups of the native layout, 8 lanes per site (lanes t < 4 the first group, t >= 4 the
+// second), and walks the block in passes of 128 sites, so that a site's links and clover are
+// loaded once for 8 right-hand sides; lanes of a group beyond the last one do nothing.
+template <typename Ts, typename Tc>
+__global__ void __launch_bounds__(1024) k_dirac_2g(KGeo g, const Tc *__restrict__ links, const Tc *__restrict__ clover,
+                                                   const uint32_t *__restrict__ blk_coords,
+                                                   const uint32_t *__restrict__ loc_coords, const Ts *__restrict__ x,
+                                                   Ts *__restrict__ y, int ntiles, int ngrp)
+{
+    const int li = xcd_remap(blockIdx.x, g.nblk * ntiles);
+    const int blk = li / ntiles, tile = li - blk * ntiles;
+    const int lt = tile * 8 + threadIdx.x % 8, grp = lt / g.S, tt = lt % g.S;
+    const int nsite = g.Vb < 128 ? g.Vb : 128;
+#pragma unroll 1
+    for (int o = threadIdx.x / 8; o < g.Vb && grp < ngrp; o += nsite) {
+        const int off = opaque_index(o);
+        int bc[4], lc[4];
+        decode_site(g, blk_coords, loc_coords, blk, off, bc, lc);
+        Spinor<Tc> out;
+        dirac_site_global<Tc>(g, links, clover, x, grp, tt, blk, off, bc, lc, out, NoSkip{});
+        store_spinor(g, y, grp, blk, off, tt, out);
+    }
+}
+
 // Per (block, tile of T right-hand sides): partial sums of |b - D x|^2 and |b|^2 per
 // right-hand side, FP64.  A workgroup of (up to 64 sites) x T lanes walks the block in
 // passes of 64 sites, so that a workgroup is small while the FP64 stencil takes ~130
@@ -148,6 +173,12 @@ int dirac_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const v
     case 4:
         // tile 4 only with FP32 arithmetic (FP64 would spill to scratch)
         if constexpr (sizeof(Tc) == 4) {
+            if (g.S == 4) {
+                const int nt2 = (ngrp + 1) / 2, ns = g.Vb < 128 ? g.Vb : 128;
+                hipLaunchKernelGGL((k_dirac_2g<Ts, Tc>), dim3(g.nblk * nt2), dim3(round64(ns * 8)), 0, st, g, links,
+                                   clover, op->blk_coords, op->loc_coords, (const Ts *)x, (Ts *)y, nt2, ngrp);
+                break;
+            }
             hipLaunchKernelGGL((k_dirac<Ts, Tc, 4>), grid, block, 0, st, g, links, clover, op->blk_coords,
                                op->loc_coords, (const Ts *)x, (Ts *)y, ntiles);
             break;
