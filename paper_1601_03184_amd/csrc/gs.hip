@@ -231,25 +231,28 @@ template <int NT> __device__ inline void gram_reduce(const GramAcc &acc, Cplx *G
 // lane l holds row b0 + 4j + l/16 of columns 16 t + l%16.
 template <typename Tv, int NT> struct GramRaw {
     Tv v[4][NT][2];
+    uint32_t ok;  // bit NT j + t: the operand (j, t) is in range (else it reads as zero)
 };
 
 template <typename Tv, int NT>
 __device__ inline void load_gram(const Tv *V, const uint32_t *sbase, const size_t *coff, int h, uint32_t cstr, int b0,
                                  int nrows, int N, int lane, GramRaw<Tv, NT> &o)
 {
+    o.ok = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int n = b0 + 4 * j + (lane >> 4);
         const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            // out-of-range operands read element 0 and are replaced by zero
+            // out-of-range operands read element 0; the products take them as zero, so that
+            // nothing here waits for the loads
             const int k = 16 * t + (lane & 15);
             const bool ok = n < nrows && k < N;
             const size_t idx = ok ? ro + coff[k] : 0;
-            const Tv re = V[idx], im = V[ok ? idx + cstr : 0];
-            o.v[j][t][0] = ok ? re : Tv(0);
-            o.v[j][t][1] = ok ? im : Tv(0);
+            o.v[j][t][0] = V[idx];
+            o.v[j][t][1] = V[ok ? idx + cstr : 0];
+            o.ok |= (uint32_t)ok << (NT * j + t);
         }
     }
 }
@@ -261,8 +264,9 @@ template <typename Tv, int NT> __device__ inline void gram_block(const GramRaw<T
         double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            xr[t] = to_f64(o.v[j][t][0]);
-            xi[t] = to_f64(o.v[j][t][1]);
+            const bool ok = (o.ok >> (NT * j + t)) & 1u;
+            xr[t] = ok ? to_f64(o.v[j][t][0]) : 0.0;
+            xi[t] = ok ? to_f64(o.v[j][t][1]) : 0.0;
         }
         gram_step<NT>(xr, xi, acc);
         __builtin_amdgcn_sched_barrier(0);
@@ -273,6 +277,7 @@ template <typename Tv, int NT> __device__ inline void gram_block(const GramRaw<T
 // 4 ks + l/16.
 template <typename Tv, int NT> struct TransRaw {
     Tv v[4 * NT][2];
+    uint32_t ok;  // bit ks: the operand ks is in range (else it reads as zero)
 };
 
 template <typename Tv, int NT>
@@ -281,14 +286,15 @@ __device__ inline void load_trans(const Tv *V, const uint32_t *sbase, const size
 {
     const int n = b0 + (lane & 15);
     const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
+    o.ok = 0;
 #pragma unroll
     for (int ks = 0; ks < 4 * NT; ++ks) {
         const int k = 4 * ks + (lane >> 4);
         const bool ok = n < nrows && k < N;
         const size_t idx = ok ? ro + coff[k] : 0;
-        const Tv re = V[idx], im = V[ok ? idx + cstr : 0];
-        o.v[ks][0] = ok ? re : Tv(0);
-        o.v[ks][1] = ok ? im : Tv(0);
+        o.v[ks][0] = V[idx];
+        o.v[ks][1] = V[ok ? idx + cstr : 0];
+        o.ok |= (uint32_t)ok << ks;
     }
 }
 
@@ -305,7 +311,8 @@ __device__ inline void trans_block(const TransRaw<Tv, NT> &o, const Cplx *M, int
 #pragma unroll
     for (int ks = 0; ks < NT * 4; ++ks) {
         const int k = 4 * ks + (lane >> 4);  // column of V = row of M
-        const double vr = to_f64(o.v[ks][0]), vi = to_f64(o.v[ks][1]), vs = vr + vi;
+        const bool ok = (o.ok >> ks) & 1u;
+        const double vr = ok ? to_f64(o.v[ks][0]) : 0.0, vi = ok ? to_f64(o.v[ks][1]) : 0.0, vs = vr + vi;
 #pragma unroll
         for (int tj = 0; tj < NT; ++tj) {
             if (ks * 4 >= (tj + 1) * 16) continue;  // M is upper triangular
@@ -321,6 +328,26 @@ __device__ inline void trans_block(const TransRaw<Tv, NT> &o, const Cplx *M, int
     for (int tj = 0; tj < 2; ++tj) {
         dr[tj] = t1[tj] - t2[tj];
         di[tj] = t3[tj] - t1[tj] - t2[tj];
+    }
+}
+
+// Runs body(operands, b0) for the 16-row blocks b0 = first, first + step, ... < nrows, with the
+// loads of each block issued before the products of the previous one.  Two operand sets take
+// turns, so that no register copy has to wait for loads still in flight.
+template <typename Raw, typename Load, typename Body>
+__device__ inline void pipelined_blocks(int first, int step, int nrows, Load load, Body body)
+{
+    Raw ra, rb;
+    int b0 = first;
+    if (b0 < nrows) load(b0, ra);
+    while (b0 < nrows) {
+        if (b0 + step < nrows) load(b0 + step, rb);
+        body(ra, b0);
+        b0 += step;
+        if (b0 >= nrows) break;
+        if (b0 + step < nrows) load(b0 + step, ra);
+        body(rb, b0);
+        b0 += step;
     }
 }
 
@@ -340,9 +367,10 @@ __device__ inline void stage_sites(const GsArgs &a, int i, int ls0, int n, uint3
 // One workgroup per (aggregate i, half h).  Every pass walks the rows in 16-row blocks,
 // NW blocks apart per wavefront, with the next block's elements loaded while the current
 // one is on the matrix cores.
-// three workgroups per CU (168 VGPRs) where the FP32 or binary16 input allows it without spilling
+// two workgroups per CU: the operands in flight across the products need more registers than
+// the 168 of three (FP32 input spilled there)
 template <typename Tv, typename Tq, int NT>
-__global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsArgs a)
+__global__ void __launch_bounds__(NTHR, 2) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;
@@ -376,14 +404,10 @@ __global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsAr
             stage_sites(a, i, ls0, nsc, sbase);
             staged = ls0;
         }
-        int b0 = wave * 16;
-        GramRaw<Tv, NT> cur, nxt;
-        if (b0 < nrows) load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
-        for (; b0 < nrows; b0 += NW * 16) {
-            if (b0 + NW * 16 < nrows) load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
-            gram_block<Tv, NT>(cur, acc);
-            cur = nxt;
-        }
+        pipelined_blocks<GramRaw<Tv, NT>>(
+            wave * 16, NW * 16, nrows,
+            [&](int b0, GramRaw<Tv, NT> &o) { load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o); },
+            [&](const GramRaw<Tv, NT> &o, int) { gram_block<Tv, NT>(o, acc); });
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);
@@ -400,11 +424,10 @@ __global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsAr
             stage_sites(a, i, ls0, nsc, sbase);
             staged = ls0;
         }
-        int b0 = wave * 16;
-        TransRaw<Tv, NT> cur, nxt;
-        if (b0 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
-        for (; b0 < nrows; b0 += NW * 16) {
-            if (b0 + NW * 16 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
+        const auto load = [&](int b0, TransRaw<Tv, NT> &o) {
+            load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o);
+        };
+        pipelined_blocks<TransRaw<Tv, NT>>(wave * 16, NW * 16, nrows, load, [&](const TransRaw<Tv, NT> &cur, int) {
             d4 dr[2], di[2];
             trans_block<Tv, NT>(cur, X1, NP, lane, dr, di);
             // the 16 rows of Q1 go through this wavefront's LDS rows, from which the Gram
@@ -431,8 +454,7 @@ __global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsAr
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            cur = nxt;
-        }
+        });
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);
@@ -448,11 +470,10 @@ __global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsAr
             stage_sites(a, i, ls0, nsc, sbase);
             staged = ls0;
         }
-        int b0 = wave * 16;
-        TransRaw<Tv, NT> cur, nxt;
-        if (b0 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, cur);
-        for (; b0 < nrows; b0 += NW * 16) {
-            if (b0 + NW * 16 < nrows) load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0 + NW * 16, nrows, N, lane, nxt);
+        const auto load = [&](int b0, TransRaw<Tv, NT> &o) {
+            load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o);
+        };
+        pipelined_blocks<TransRaw<Tv, NT>>(wave * 16, NW * 16, nrows, load, [&](const TransRaw<Tv, NT> &cur, int b0) {
             d4 dr[2], di[2];
             trans_block<Tv, NT>(cur, G, NP, lane, dr, di);
 #pragma unroll
@@ -469,8 +490,7 @@ __global__ void __launch_bounds__(NTHR, sizeof(Tv) == 8 ? 2 : 3) k_block_gs(GsAr
                     Q[idx + cstr] = store_as<Tq>(di[tj][r]);
                 }
             }
-            cur = nxt;
-        }
+        });
     }
     __syncthreads();
     if (threadIdx.x == 0 && bad && a.status) atomicMin(a.status, 1 + (int)blockIdx.x);
