@@ -28,6 +28,8 @@ constexpr int NW = NTHR / 64;
 constexpr int CHS = 8;  // sites per LDS chunk
 constexpr int MAXVA = 256;
 constexpr int MAXFACE = 64;  // face sites of an aggregate whose neighbours the table holds
+constexpr int MAXN = 32;     // test vectors
+constexpr int QST = MAXN + 1, WST = 2 * MAXN + 1;  // LDS row strides (pairs) of rows and columns
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
@@ -179,27 +181,50 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
 
+// the K steps of one chunk for the wavefront's first NTL tiles: conj(q) w accumulated as four
+// real products per complex one, straight-line so that the LDS reads of later steps are in
+// flight during the products of earlier ones
+template <int NTL>
+__device__ inline void tile_products(const float2 *const (&qb)[2], const float2 *const (&wb)[2], f4 (&accr)[2],
+                                     f4 (&acci)[2])
+{
+#pragma unroll
+    for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
+#pragma unroll
+        for (int m = 0; m < NTL; ++m) {
+            const float2 q = qb[m][kk0 * QST], w = wb[m][kk0 * WST];
+            accr[m] = mfma32(q.x, w.x, accr[m]);
+            acci[m] = mfma32(q.x, w.y, acci[m]);
+            accr[m] = mfma32(q.y, w.y, accr[m]);
+            acci[m] = mfma32(-q.y, w.x, acci[m]);
+        }
+    }
+}
+
 template <typename Tc, typename Tq>
 __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__restrict__ links,
                                                  const Tc *__restrict__ clover)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N, N2 = 2 * N;
-    // rows of Qs and Ws are padded by one pair, so that the four rows a matrix-core step
-    // reads fall on different LDS banks
-    const int QST = N + 1, WST = 2 * N + 1;
+    // Qs and Ws rows are (half, site, component within the half): the K rows of one half are
+    // contiguous.  The strides are those of 32 vectors plus one pair (the four rows a
+    // matrix-core step reads fall on different LDS banks), so every product read has a fixed
+    // offset; entries beyond N (2N) are never written and only reach output rows (columns)
+    // that are not stored.
     SiteRef *tab = reinterpret_cast<SiteRef *>(smem);  // [MAXVA] own sites, [MAXFACE] face neighbours
-    float2 *Qs = reinterpret_cast<float2 *>(tab + MAXVA + MAXFACE);  // [CHS][12][QST]
-    float2 *Ws = Qs + CHS * 12 * QST;                               // [CHS][12][WST]
+    float2 *Qs = reinterpret_cast<float2 *>(tab + MAXVA + MAXFACE);  // [2][CHS][6][QST]
+    float2 *Ws = Qs + CHS * 12 * QST;                               // [2][CHS][6][WST]
     // blockIdx.y = 0: the self block; 1 + mu: the +mu face block
     const int i = blockIdx.x, d = blockIdx.y;
     const bool self = d == 0;
     const int mu = d - 1;
     const int nsites = self ? a.Va : a.Va / a.a[mu];
     int j = i;  // the aggregate across the +mu face
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int TR = (N + 15) / 16, TC = (N2 + 15) / 16, ntile = 2 * TR * TC;
     constexpr int MAXT = (16 + NW - 1) / NW;  // tiles per wavefront (N <= 32: at most 16 tiles)
+    static_assert(MAXT == 2, "the product loop takes two tiles per wavefront");
     f4 accr[MAXT], acci[MAXT];
 #pragma unroll
     for (int m = 0; m < MAXT; ++m) accr[m] = acci[m] = f4{0.f, 0.f, 0.f, 0.f};
@@ -240,7 +265,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
                     v = make_float2(load_as<float>(qk + vo + (2 * comp) * cs),
                                     load_as<float>(qk + vo + (2 * comp + 1) * cs));
                 }
-                Qs[rw * QST + kt] = v;
+                Qs[((comp >= 6 ? CHS * 6 : 0) + sl * 6 + comp % 6) * QST + kt] = v;
             }
             // columns: (h', site) pairs, k' = kt; h' outermost, so that a wavefront mostly
             // shares one spin half
@@ -257,29 +282,24 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
                 const int c = hp * N + kt;
 #pragma unroll
                 for (int comp = 0; comp < 12; ++comp)
-                    Ws[(sl * 12 + comp) * WST + c] = make_float2((float)w.re[comp], (float)w.im[comp]);
+                    Ws[((comp / 6) * CHS * 6 + sl * 6 + comp % 6) * WST + c] =
+                        make_float2((float)w.re[comp], (float)w.im[comp]);
             }
         }
         __syncthreads();
+        // the wavefront's tiles in one K loop: four independent accumulator chains; K row kk of
+        // half h is LDS row h CHS 6 + kk
+        const float2 *qb[MAXT], *wb[MAXT];
 #pragma unroll
         for (int m = 0; m < MAXT; ++m) {
-            const int tile = wave + NW * m;
-            if (tile >= ntile) break;
+            const int tile = std::min(wave + NW * m, ntile - 1);
             const int h = tile / (TR * TC), rem = tile - h * TR * TC, tr = rem / TC, tc = rem - tr * TC;
-            const int k = tr * 16 + (lane & 15);   // output row within the half (A row)
-            const int c = tc * 16 + (lane & 15);   // output column (B column)
-#pragma unroll 1
-            for (int kk0 = 0; kk0 < CHS * 6; kk0 += 4) {
-                const int kk = kk0 + (lane >> 4), sl = kk / 6, comp = 6 * h + kk % 6;
-                const float2 qv = k < N ? Qs[(sl * 12 + comp) * QST + k] : make_float2(0.f, 0.f);
-                const float2 w = c < N2 ? Ws[(sl * 12 + comp) * WST + c] : make_float2(0.f, 0.f);
-                // conj(q) w
-                accr[m] = mfma32(qv.x, w.x, accr[m]);
-                accr[m] = mfma32(qv.y, w.y, accr[m]);
-                acci[m] = mfma32(qv.x, w.y, acci[m]);
-                acci[m] = mfma32(-qv.y, w.x, acci[m]);
-            }
+            const int r0 = h * CHS * 6 + (lane >> 4);
+            qb[m] = Qs + r0 * QST + tr * 16 + (lane & 15);  // A: conj(q) rows k of the half
+            wb[m] = Ws + r0 * WST + tc * 16 + (lane & 15);  // B: columns c
         }
+        if (wave + NW < ntile) tile_products<2>(qb, wb, accr, acci);
+        else if (wave < ntile) tile_products<1>(qb, wb, accr, acci);
     }
     // D_c(i, i) or D_c(i, i + mu); for a face also D_c(i + mu, i) = sigma3 D_c(i, i + mu)^dag sigma3
     // into the -mu slot of aggregate j = i + mu (each slot has exactly one writer)
@@ -372,7 +392,7 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     for (int mu = 0; mu < 4; ++mu)
         if (op->Va / op->g.agg[mu] > MAXFACE)
             return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate face above 64 sites");
-    const size_t lds = sizeof(SiteRef) * (MAXVA + MAXFACE) + sizeof(float2) * (size_t)CHS * 12 * (3 * n_tv + 2);
+    const size_t lds = sizeof(SiteRef) * (MAXVA + MAXFACE) + sizeof(float2) * (size_t)CHS * 12 * (QST + WST);
     hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a, links, clover);
     return hip_check(hipGetLastError(), "k_coarse launch");
 }
