@@ -30,6 +30,7 @@ constexpr int MAXVA = 256;
 constexpr int MAXFACE = 64;  // face sites of an aggregate whose neighbours the table holds
 constexpr int MAXN = 32;     // test vectors
 constexpr int QST = MAXN + 1, WST = 2 * MAXN + 1;  // LDS row strides (pairs) of rows and columns
+constexpr int RMAX = (CHS * 12 + NTHR / MAXN - 1) / (NTHR / MAXN);  // rows per thread and chunk
 
 template <typename Tq> struct CoarseArgs {
     KGeo g;
@@ -176,7 +177,10 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *__restrict
 // (site, component) rows, and complex = 4 real products.  Lane l supplies
 // A[l%16][l/16] = conj(q)[row][kk] and B[l/16][l%16] = w[kk][col], holds D[4(l/16)+r][l%16].
 // The sites the workgroup touches are looked up once into an LDS table (native index,
-// vector offset, local coordinates), so the per-item work has no integer division.
+// vector offset, local coordinates), so the per-item work has no integer division.  The
+// rows of the next chunk are loaded during the products of the current one, and the
+// aggregates are taken in contiguous runs per XCD, so that concurrent workgroups of one
+// XCD read neighbouring aggregates (the face parts' neighbours) through the same L2.
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
@@ -216,7 +220,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     float2 *Qs = reinterpret_cast<float2 *>(tab + MAXVA + MAXFACE);  // [2][CHS][6][QST]
     float2 *Ws = Qs + CHS * 12 * QST;                               // [2][CHS][6][WST]
     // blockIdx.y = 0: the self block; 1 + mu: the +mu face block
-    const int i = blockIdx.x, d = blockIdx.y;
+    const int i = xcd_remap(blockIdx.x, gridDim.x), d = blockIdx.y;  // aggregates in runs per XCD
     const bool self = d == 0;
     const int mu = d - 1;
     const int nsites = self ? a.Va : a.Va / a.a[mu];
@@ -253,20 +257,36 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     const Tq *qk = a.Q + (size_t)(kt >> a.sshift) * a.gsz + (kt & ((1 << a.sshift) - 1));
     const uint32_t cs = (uint32_t)(a.g.Vb * a.g.S);
 
+    // rows: q_k at (site, component) of a chunk, one (site, component) row per thread and pass.
+    // The next chunk's rows are loaded into registers before the products of the current one
+    // and stored to LDS after them; a row outside the set reads site 0 and is stored as zero.
+    float2 rv[RMAX];
+    uint32_t rok = 0;
+    const auto load_rows = [&](int s0) {
+        rok = 0;
+#pragma unroll
+        for (int it = 0; it < RMAX; ++it) {
+            const int rw = prow + it * rows_per_pass, sl = rw / 12, comp = rw - sl * 12, sidx = s0 + sl;
+            const bool ok = prow < rows_per_pass && rw < CHS * 12 && sidx < nsites;
+            const uint32_t vo = tab[ok ? sidx : 0].vo;
+            const int cc = ok ? comp : 0;
+            rv[it] = make_float2(load_as<float>(qk + vo + (2 * cc) * cs), load_as<float>(qk + vo + (2 * cc + 1) * cs));
+            rok |= (uint32_t)ok << it;
+        }
+    };
+    __syncthreads();  // the site table
+    load_rows(0);
+
     for (int s0 = 0; s0 < nsites; s0 += CHS) {
         __syncthreads();
-        // rows: conj(q_k) at (site, component), one (site, component) row per thread and pass
+#pragma unroll
+        for (int it = 0; it < RMAX; ++it) {
+            const int rw = prow + it * rows_per_pass, sl = rw / 12, comp = rw - sl * 12;
+            if (prow < rows_per_pass && rw < CHS * 12)
+                Qs[((comp >= 6 ? CHS * 6 : 0) + sl * 6 + comp % 6) * QST + kt] =
+                    (rok >> it) & 1u ? rv[it] : make_float2(0.f, 0.f);
+        }
         if (prow < rows_per_pass) {
-            for (int rw = prow; rw < CHS * 12; rw += rows_per_pass) {
-                const int sl = rw / 12, comp = rw - sl * 12, sidx = s0 + sl;
-                float2 v = make_float2(0.f, 0.f);
-                if (sidx < nsites) {
-                    const uint32_t vo = tab[sidx].vo;
-                    v = make_float2(load_as<float>(qk + vo + (2 * comp) * cs),
-                                    load_as<float>(qk + vo + (2 * comp + 1) * cs));
-                }
-                Qs[((comp >= 6 ? CHS * 6 : 0) + sl * 6 + comp % 6) * QST + kt] = v;
-            }
             // columns: (h', site) pairs, k' = kt; h' outermost, so that a wavefront mostly
             // shares one spin half
             for (int pr = prow; pr < 2 * CHS; pr += rows_per_pass) {
@@ -287,6 +307,7 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
             }
         }
         __syncthreads();
+        if (s0 + CHS < nsites) load_rows(s0 + CHS);
         // the wavefront's tiles in one K loop: four independent accumulator chains; K row kk of
         // half h is LDS row h CHS 6 + kk
         const float2 *qb[MAXT], *wb[MAXT];

@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(NTHR, 2) k_block_gs(GsArgs a)
 
     const Tv *V = static_cast<const Tv *>(a.V);
     Tq *Q = static_cast<Tq *>(a.Q);
-    const int i = blockIdx.x >> 1, h = blockIdx.x & 1;
+    const int wi = xcd_remap(blockIdx.x, gridDim.x), i = wi >> 1, h = wi & 1;  // runs per XCD
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t cstr = (uint32_t)a.g.Vb * (uint32_t)a.g.S;
     const size_t gstr = (size_t)a.g.nblk * 24 * cstr;  // one group of S test vectors

@@ -29,6 +29,15 @@ struct KGeo {
 
 __host__ __device__ inline int unpack_coord(uint32_t p, int mu) { return (p >> (8 * mu)) & 0xff; }
 
+// XCD-aware workgroup order: consecutive workgroups are dispatched round-robin over the
+// 8 XCDs, so list entry li is given to workgroup w such that each XCD receives a
+// contiguous run of the list (neighbouring work items share that XCD's L2).
+__device__ inline int xcd_remap(int w, int nwg)
+{
+    const int q = nwg >> 3, r = nwg & 7, xcd = w & 7, slot = w >> 3;
+    return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
 struct mrhs_op {
     mrhs_geom g;
     KGeo k;

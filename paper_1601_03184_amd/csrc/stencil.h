@@ -34,15 +34,6 @@ template <typename T> __device__ inline void hop_fence(Spinor<T> &s)
     sched_fence();
 }
 
-// XCD-aware workgroup order: consecutive workgroups are dispatched round-robin over the
-// 8 XCDs, so list entry li is given to workgroup w such that each XCD receives a
-// contiguous run of the list (the right-hand-side tiles of one block share that XCD's L2).
-__device__ inline int xcd_remap(int w, int nwg)
-{
-    const int q = nwg >> 3, r = nwg & 7, xcd = w & 7, slot = w >> 3;
-    return xcd * q + (xcd < r ? xcd : r) + slot;
-}
-
 __device__ inline void decode_site(const KGeo &g, const uint32_t *__restrict__ blk_coords,
                                    const uint32_t *__restrict__ loc_coords, int blk, int off, int (&bc)[4], int (&lc)[4])
 {
