@@ -29,7 +29,9 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NTHR = 256;  // 4 wavefronts
 constexpr int NW = NTHR / 64;
-constexpr int SCH = 1024;  // aggregate sites whose row offsets are staged in LDS at a time
+// aggregate sites whose row offsets are staged in LDS at a time (a 4^4 aggregate in one go;
+// at 256 the LDS of three workgroups fits in a CU)
+constexpr int SCH = 256;
 
 struct GsArgs {
     KGeo g;
@@ -365,12 +367,12 @@ __device__ inline void stage_sites(const GsArgs &a, int i, int ls0, int n, uint3
 }
 
 // One workgroup per (aggregate i, half h).  Every pass walks the rows in 16-row blocks,
-// NW blocks apart per wavefront, with the next block's elements loaded while the current
-// one is on the matrix cores.
-// two workgroups per CU: the operands in flight across the products need more registers than
-// the 168 of three (FP32 input spilled there)
+// NW blocks apart per wavefront; the first and the last pass load the next block's elements
+// while the current one is on the matrix cores.  Three workgroups per CU (at most 168
+// VGPRs): the second pass, whose Gram accumulators are live beside the transform's, loads
+// each block right before its products, which keeps it within that budget without spilling.
 template <typename Tv, typename Tq, int NT>
-__global__ void __launch_bounds__(NTHR, 2) k_block_gs(GsArgs a)
+__global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;
@@ -427,7 +429,9 @@ __global__ void __launch_bounds__(NTHR, 2) k_block_gs(GsArgs a)
         const auto load = [&](int b0, TransRaw<Tv, NT> &o) {
             load_trans<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o);
         };
-        pipelined_blocks<TransRaw<Tv, NT>>(wave * 16, NW * 16, nrows, load, [&](const TransRaw<Tv, NT> &cur, int) {
+        for (int b0 = wave * 16; b0 < nrows; b0 += NW * 16) {
+            TransRaw<Tv, NT> cur;
+            load(b0, cur);
             d4 dr[2], di[2];
             trans_block<Tv, NT>(cur, X1, NP, lane, dr, di);
             // the 16 rows of Q1 go through this wavefront's LDS rows, from which the Gram
@@ -454,7 +458,7 @@ __global__ void __launch_bounds__(NTHR, 2) k_block_gs(GsArgs a)
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-        });
+        }
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);

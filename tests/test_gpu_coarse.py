@@ -38,6 +38,7 @@ GS_CASES = [
     ([4, 4, 4, 8], [2, 2, 2, 2], [4, 4, 4, 4], F64, 2, 32, D64, D64, False, False),  # aggregate = 16 blocks
     ([8, 8, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F32, 4, 20, D32, D16, False, True),   # FP16 storage of Q
     ([8, 4, 4, 8], [4, 4, 4, 4], [4, 4, 4, 4], F16, 4, 24, D16, D16, True, False),   # FP16 in place
+    ([8, 4, 4, 16], [4, 4, 4, 4], [4, 4, 4, 8], F32, 4, 12, D32, D64, False, False),  # 512 sites: two stagings
 ]
 
 
