@@ -61,6 +61,10 @@ DIRAC_CASES = [
     ([12, 4, 8, 4], [4, 4, 4, 4], 0.25, 121, -0.33, F16, 4, 7, 4),
     ([6, 6, 2, 4], [2, 2, 2, 2], 0.3, 131, -0.2, F32, 8, 9, 4),   # odd block counts, ragged
     ([4, 2, 2, 4], [4, 2, 2, 2], 0.3, 141, 0.2, F64, 2, 3, 2),    # a block spans a direction
+    # tile 4 on a short length of 4 (two groups per workgroup): 16-site blocks and an odd
+    # number of groups, and 24-site blocks (a workgroup of 192 threads)
+    ([4, 4, 4, 4], [2, 2, 2, 2], 0.3, 151, -0.2, F32, 4, 11, 4),
+    ([4, 4, 4, 6], [2, 2, 2, 3], 0.3, 161, -0.25, F32, 4, 13, 4),
 ]
 
 
