@@ -377,12 +377,10 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int NP = NT * 16;
     const int N = a.n_tv;
-    constexpr int UNION = 2 * NP * NP > 64 * NP ? 2 * NP * NP : 64 * NP;
     Cplx *X1 = reinterpret_cast<Cplx *>(smem);  // R1^-1
     Cplx *G = X1 + NP * NP;                      // Gram matrix / Cholesky factor / R1^-1 R2^-1
     Cplx *X2 = G + NP * NP;                      // R2^-1
-    Cplx *Qw = G;  // during the second Gram pass: 16 rows of Q1 per wavefront (over G and X2)
-    double *diag0 = reinterpret_cast<double *>(G + UNION);
+    double *diag0 = reinterpret_cast<double *>(X2 + NP * NP);
     size_t *coff = reinterpret_cast<size_t *>(diag0 + NP);
     uint32_t *sbase = reinterpret_cast<uint32_t *>(coff + NP);
     __shared__ int bad;
@@ -434,30 +432,20 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
             load(b0, cur);
             d4 dr[2], di[2];
             trans_block<Tv, NT>(cur, X1, NP, lane, dr, di);
-            // the 16 rows of Q1 go through this wavefront's LDS rows, from which the Gram
-            // product reads them in its own operand layout
-            Cplx *qw = Qw + wave * 16 * NP;
-#pragma unroll
-            for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    qw[((lane >> 4) + 4 * r) * NP + 16 * tj + (lane & 15)] = {dr[tj][r], di[tj][r]};
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+            // the transform leaves row b0 + l/16 + 4r of column 16 t + l%16 in register r of
+            // lane l, which is where K step r of the Gram product takes its operand: the 16
+            // rows of Q1 go from the accumulators straight into the Gram product
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    const Cplx q = qw[(4 * j + (lane >> 4)) * NP + 16 * t + (lane & 15)];
-                    xr[t] = q.re;
-                    xi[t] = q.im;
+                    xr[t] = dr[t][j];
+                    xi[t] = di[t][j];
                 }
                 gram_step<NT>(xr, xi, acc);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
     }
     __syncthreads();
@@ -508,8 +496,7 @@ __global__ void k_status_final(int32_t *s)
 
 size_t gs_lds(int NP)
 {
-    const size_t uni = std::max(2 * NP * NP, 64 * NP);
-    return sizeof(Cplx) * (NP * NP + uni) + (sizeof(double) + sizeof(size_t)) * NP + 4 * SCH;
+    return sizeof(Cplx) * 3 * NP * NP + (sizeof(double) + sizeof(size_t)) * NP + 4 * SCH;
 }
 
 template <typename Tv, typename Tq, int NT> int launch_typed(const GsArgs &a, int n_agg, size_t max_lds, hipStream_t st)
