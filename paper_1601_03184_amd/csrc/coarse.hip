@@ -168,7 +168,7 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *__restrict
     }
 }
 
-// grid: (aggregate i, part: self, then +mu).  A 2N x 2N block is a sum over the
+// grid: 5 items per aggregate (self, then +mu).  A 2N x 2N block is a sum over the
 // block's sites and the 6 components of each spin half: rows (h, k) = conj(q_k) of half h,
 // columns c = (h', k') the stencil part d applied to P_c.  Both are formed a chunk of CHS
 // sites at a time in LDS (the columns by one thread per (h', site, k')); the
@@ -179,8 +179,9 @@ __device__ inline void part_column(const CoarseArgs<Tq> &a, const Tc *__restrict
 // The sites the workgroup touches are looked up once into an LDS table (native index,
 // vector offset, local coordinates), so the per-item work has no integer division.  The
 // rows of the next chunk are loaded during the products of the current one, and the
-// aggregates are taken in contiguous runs per XCD, so that concurrent workgroups of one
-// XCD read neighbouring aggregates (the face parts' neighbours) through the same L2.
+// (aggregate, part) items are taken in contiguous runs per XCD, so that concurrent
+// workgroups of one XCD read neighbouring aggregates (the face parts' neighbours) through
+// the same L2, and the vector-unit-heavy self parts share CUs with the latency-bound faces.
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline f4 mfma32(float x, float y, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0); }
@@ -219,8 +220,10 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     SiteRef *tab = reinterpret_cast<SiteRef *>(smem);  // [MAXVA] own sites, [MAXFACE] face neighbours
     float2 *Qs = reinterpret_cast<float2 *>(tab + MAXVA + MAXFACE);  // [2][CHS][6][QST]
     float2 *Ws = Qs + CHS * 12 * QST;                               // [2][CHS][6][WST]
-    // blockIdx.y = 0: the self block; 1 + mu: the +mu face block
-    const int i = xcd_remap(blockIdx.x, gridDim.x), d = blockIdx.y;  // aggregates in runs per XCD
+    // work item li = 5 i + d: aggregate i, part d (0: the self block; 1 + mu: the +mu face
+    // block), so that the five parts of an aggregate are consecutive and a CU runs self and
+    // face workgroups side by side; items in contiguous runs per XCD
+    const int li = xcd_remap(blockIdx.x, gridDim.x), i = li / 5, d = li - 5 * i;
     const bool self = d == 0;
     const int mu = d - 1;
     const int nsites = self ? a.Va : a.Va / a.a[mu];
@@ -414,7 +417,7 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
         if (op->Va / op->g.agg[mu] > MAXFACE)
             return set_error(MRHS_EUNSUPPORTED, "coarse_op_build: aggregate face above 64 sites");
     const size_t lds = sizeof(SiteRef) * (MAXVA + MAXFACE) + sizeof(float2) * (size_t)CHS * 12 * (QST + WST);
-    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg, 5), dim3(NTHR), lds, st, a, links, clover);
+    hipLaunchKernelGGL((k_coarse<Tc, Tq>), dim3(op->n_agg * 5), dim3(NTHR), lds, st, a, links, clover);
     return hip_check(hipGetLastError(), "k_coarse launch");
 }
 
