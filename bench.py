@@ -717,7 +717,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="only run a plain 1 GiB device copy (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (it would shard the "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (it would shard the "
               "lattice by domain decomposition, one halo exchange per SAP half-sweep)", file=sys.stderr)
         sys.exit(2)
     assert torch.cuda.is_available(), "bench needs a GPU"
