@@ -160,31 +160,42 @@ __device__ void tri_product(const Cplx *A, const Cplx *B, Cplx *C, int NP)
 // Gram accumulators of the tile pairs (0,0), (0,1), (1,1), real and imaginary part.  A
 // diagonal pair needs three real products per K step, not four: Re = Xr^T Xr + Xi^T Xi,
 // and for the imaginary part only P = Xr^T Xi, whose antisymmetric part P - P^T it is
-// (taken once the wavefronts' tiles are summed, gram_fix_diag); the off-diagonal pair takes
-// Xr^T Xi - Xi^T Xr in full.
-struct GramAcc {
-    d4 re[3], im[3];
+// (taken once the wavefronts' tiles are summed, gram_fix_diag).  The off-diagonal pair takes
+// Xr^T Xi - Xi^T Xr in full, or (G3) three real products as well (Gauss): t1 = Xr^T Xr',
+// t2 = Xi^T Xi', t3 = (Xr + Xi)^T (Xr' - Xi'), Re = t1 + t2, Im = t1 - t2 - t3, with re
+// holding t1 and im t2 until the tiles are written out.  G3 costs one more accumulator; the
+// kernel for FP64 input, at its register limit, keeps the four-product form.
+template <bool G3> struct GramAcc {
+    d4 re[3], im[3], t3;
     __device__ void zero()
     {
 #pragma unroll
         for (int p = 0; p < 3; ++p) re[p] = im[p] = d4{0.0, 0.0, 0.0, 0.0};
+        if (G3) t3 = d4{0.0, 0.0, 0.0, 0.0};
     }
 };
 
 __device__ inline int pair_index(int ti, int tj) { return ti == 0 ? tj : 2; }
 
 // G += x^dag x for one K step, x the operands of the NT column tiles
-template <int NT> __device__ inline void gram_step(const double (&xr)[2], const double (&xi)[2], GramAcc &acc)
+template <int NT, bool G3>
+__device__ inline void gram_step(const double (&xr)[2], const double (&xi)[2], GramAcc<G3> &acc)
 {
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
         for (int tj = ti; tj < NT; ++tj) {
             const int p = pair_index(ti, tj);
-            acc.re[p] = mfma(xr[ti], xr[tj], acc.re[p]);
-            acc.re[p] = mfma(xi[ti], xi[tj], acc.re[p]);
-            acc.im[p] = mfma(xr[ti], xi[tj], acc.im[p]);
-            if (ti != tj) acc.im[p] = mfma(-xi[ti], xr[tj], acc.im[p]);
+            if (G3 && ti != tj) {
+                acc.re[p] = mfma(xr[ti], xr[tj], acc.re[p]);
+                acc.im[p] = mfma(xi[ti], xi[tj], acc.im[p]);
+                acc.t3 = mfma(xr[ti] + xi[ti], xr[tj] - xi[tj], acc.t3);
+            } else {
+                acc.re[p] = mfma(xr[ti], xr[tj], acc.re[p]);
+                acc.re[p] = mfma(xi[ti], xi[tj], acc.re[p]);
+                acc.im[p] = mfma(xr[ti], xi[tj], acc.im[p]);
+                if (ti != tj) acc.im[p] = mfma(-xi[ti], xr[tj], acc.im[p]);
+            }
         }
 }
 
@@ -200,7 +211,8 @@ template <int NT> __device__ inline void gram_fix_diag(Cplx *G, int NP)
 }
 
 // add (or, for the first wavefront, write) this wavefront's Gram tiles into G
-template <int NT> __device__ inline void gram_accumulate(const GramAcc &acc, Cplx *G, int NP, int lane, bool first)
+template <int NT, bool G3>
+__device__ inline void gram_accumulate(const GramAcc<G3> &acc, Cplx *G, int NP, int lane, bool first)
 {
 #pragma unroll
     for (int ti = 0; ti < NT; ++ti)
@@ -211,6 +223,7 @@ template <int NT> __device__ inline void gram_accumulate(const GramAcc &acc, Cpl
             for (int r = 0; r < 4; ++r) {
                 const int row = ti * 16 + (lane >> 4) + 4 * r, col = tj * 16 + (lane & 15);
                 Cplx v = {acc.re[p][r], acc.im[p][r]};
+                if (G3 && ti != tj) v = {acc.re[p][r] + acc.im[p][r], acc.re[p][r] - acc.im[p][r] - acc.t3[r]};
                 if (!first) {
                     v.re += G[row * NP + col].re;
                     v.im += G[row * NP + col].im;
@@ -221,7 +234,8 @@ template <int NT> __device__ inline void gram_accumulate(const GramAcc &acc, Cpl
 }
 
 // the wavefronts' partial Gram matrices summed into G in a fixed order
-template <int NT> __device__ inline void gram_reduce(const GramAcc &acc, Cplx *G, int NP, int lane, int wave)
+template <int NT, bool G3>
+__device__ inline void gram_reduce(const GramAcc<G3> &acc, Cplx *G, int NP, int lane, int wave)
 {
     for (int w = 0; w < NW; ++w) {
         if (wave == w) gram_accumulate<NT>(acc, G, NP, lane, w == 0);
@@ -259,7 +273,8 @@ __device__ inline void load_gram(const Tv *V, const uint32_t *sbase, const size_
     }
 }
 
-template <typename Tv, int NT> __device__ inline void gram_block(const GramRaw<Tv, NT> &o, GramAcc &acc)
+template <typename Tv, int NT, bool G3>
+__device__ inline void gram_block(const GramRaw<Tv, NT> &o, GramAcc<G3> &acc)
 {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -396,7 +411,8 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
     int staged = -1;  // first site of the staged range
 
     // G1 = V^dag V
-    GramAcc acc;
+    constexpr bool G3 = sizeof(Tv) < 8;  // the Gauss form of the off-diagonal Gram tile
+    GramAcc<G3> acc;
     acc.zero();
     for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
         const int nsc = std::min(SCH, a.Va - ls0), nrows = 6 * nsc;
@@ -407,7 +423,7 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
         pipelined_blocks<GramRaw<Tv, NT>>(
             wave * 16, NW * 16, nrows,
             [&](int b0, GramRaw<Tv, NT> &o) { load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o); },
-            [&](const GramRaw<Tv, NT> &o, int) { gram_block<Tv, NT>(o, acc); });
+            [&](const GramRaw<Tv, NT> &o, int) { gram_block<Tv, NT, G3>(o, acc); });
     }
     __syncthreads();
     gram_reduce<NT>(acc, G, NP, lane, wave);
