@@ -250,24 +250,25 @@ template <typename Tv, int NT> struct GramRaw {
     uint32_t ok;  // bit NT j + t: the operand (j, t) is in range (else it reads as zero)
 };
 
+// vk[t]: V plus the offset of this lane's column 16 t + l%16 (V itself beyond n_tv).  An
+// operand out of range (its row beyond nrows, its column beyond n_tv) reads a valid element
+// (row 0, or column 0's group) and the products take it as zero, so that nothing here waits
+// for the loads and no load is behind a branch.
 template <typename Tv, int NT>
-__device__ inline void load_gram(const Tv *V, const uint32_t *sbase, const size_t *coff, int h, uint32_t cstr, int b0,
+__device__ inline void load_gram(const Tv *const (&vk)[2], const uint32_t *sbase, int h, uint32_t cstr, int b0,
                                  int nrows, int N, int lane, GramRaw<Tv, NT> &o)
 {
     o.ok = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int n = b0 + 4 * j + (lane >> 4);
-        const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
+        const bool nok = n < nrows;
+        const uint32_t ro = row_off(sbase, h, cstr, nok ? n : 0);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            // out-of-range operands read element 0; the products take them as zero, so that
-            // nothing here waits for the loads
-            const int k = 16 * t + (lane & 15);
-            const bool ok = n < nrows && k < N;
-            const size_t idx = ok ? ro + coff[k] : 0;
-            o.v[j][t][0] = V[idx];
-            o.v[j][t][1] = V[ok ? idx + cstr : 0];
+            const bool ok = nok && 16 * t + (lane & 15) < N;
+            o.v[j][t][0] = vk[t][ro];
+            o.v[j][t][1] = vk[t][ro + cstr];
             o.ok |= (uint32_t)ok << (NT * j + t);
         }
     }
@@ -297,21 +298,23 @@ template <typename Tv, int NT> struct TransRaw {
     uint32_t ok;  // bit ks: the operand ks is in range (else it reads as zero)
 };
 
+// As load_gram: an operand out of range reads a valid element (row 0, or column 0's group)
+// and is taken as zero by the products; no load is behind a branch.
 template <typename Tv, int NT>
 __device__ inline void load_trans(const Tv *V, const uint32_t *sbase, const size_t *coff, int h, uint32_t cstr, int b0,
                                   int nrows, int N, int lane, TransRaw<Tv, NT> &o)
 {
     const int n = b0 + (lane & 15);
-    const uint32_t ro = n < nrows ? row_off(sbase, h, cstr, n) : 0;
+    const bool nok = n < nrows;
+    const Tv *vr = V + row_off(sbase, h, cstr, nok ? n : 0), *vi = vr + cstr;
     o.ok = 0;
 #pragma unroll
     for (int ks = 0; ks < 4 * NT; ++ks) {
         const int k = 4 * ks + (lane >> 4);
-        const bool ok = n < nrows && k < N;
-        const size_t idx = ok ? ro + coff[k] : 0;
-        o.v[ks][0] = V[idx];
-        o.v[ks][1] = V[ok ? idx + cstr : 0];
-        o.ok |= (uint32_t)ok << ks;
+        const size_t ck = k < N ? coff[k] : 0;
+        o.v[ks][0] = vr[ck];
+        o.v[ks][1] = vi[ck];
+        o.ok |= (uint32_t)(nok && k < N) << ks;
     }
 }
 
@@ -412,6 +415,12 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
 
     // G1 = V^dag V
     constexpr bool G3 = sizeof(Tv) < 8;  // the Gauss form of the off-diagonal Gram tile
+    const Tv *vk[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int k = 16 * t + (lane & 15);
+        vk[t] = V + (k < N ? (size_t)(k / a.g.S) * gstr + (k % a.g.S) : 0);
+    }
     GramAcc<G3> acc;
     acc.zero();
     for (int ls0 = 0; ls0 < a.Va; ls0 += SCH) {
@@ -422,7 +431,7 @@ __global__ void __launch_bounds__(NTHR, 3) k_block_gs(GsArgs a)
         }
         pipelined_blocks<GramRaw<Tv, NT>>(
             wave * 16, NW * 16, nrows,
-            [&](int b0, GramRaw<Tv, NT> &o) { load_gram<Tv, NT>(V, sbase, coff, h, cstr, b0, nrows, N, lane, o); },
+            [&](int b0, GramRaw<Tv, NT> &o) { load_gram<Tv, NT>(vk, sbase, h, cstr, b0, nrows, N, lane, o); },
             [&](const GramRaw<Tv, NT> &o, int) { gram_block<Tv, NT, G3>(o, acc); });
     }
     __syncthreads();
