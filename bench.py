@@ -224,8 +224,44 @@ class Setup:
                 delattr(self, a)
 
 
+def average_plaquette(U, L):
+    """Sanity statistic of a gauge field (not part of the path): the mean over sites and the six
+    planes mu < nu of Re tr(U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag) / 3, evaluated as
+    Re tr(P Q^dag) with P = U_mu(x) U_nu(x+mu) and Q = U_nu(x) U_mu(x+nu).  U: complex [4][V][3][3],
+    canonical site order (x fastest); 1 for unit links."""
+    Ul = U.reshape(4, L[3], L[2], L[1], L[0], 3, 3)
+    axis = {0: 3, 1: 2, 2: 1, 3: 0}  # lattice direction -> tensor axis of Ul[mu]
+    total = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            P = torch.matmul(Ul[mu], torch.roll(Ul[nu], shifts=-1, dims=axis[mu]).contiguous())
+            Q = torch.matmul(Ul[nu], torch.roll(Ul[mu], shifts=-1, dims=axis[nu]).contiguous())
+            total += float((P * Q.conj()).real.sum().item())
+            del P, Q
+    return total / (3.0 * 6.0 * U.shape[1])
+
+
+def platform():
+    """What the numbers were measured on: device, HIP runtime, and the shader clock if rocm-smi
+    reports it."""
+    prop = torch.cuda.get_device_properties(0)
+    out = {"device": prop.name, "arch": getattr(prop, "gcnArchName", None), "compute_units": prop.multi_processor_count,
+           "hip": torch.version.hip, "torch": torch.__version__}
+    try:
+        import subprocess
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True, timeout=20)
+        clocks = json.loads(r.stdout) if r.returncode == 0 else None
+        if clocks:
+            card = next(iter(clocks.values()))
+            out["sclk"] = card.get("sclk clock speed:") or card.get("sclk")
+    except Exception:  # a missing or slow rocm-smi leaves the clock unrecorded
+        pass
+    return out
+
+
 def time_steps(setup, steps, warmup):
-    """Returns per-step ms, wall ms and per-part ms (HIP events on the stream the kernels use)."""
+    """Returns per-step ms (mean), wall ms, per-part ms and the median, min and max of the
+    steps (HIP events on the stream the kernels use)."""
     parts = ["sap", "resid", "gs", "dc"]
     for _ in range(warmup):
         for p in parts:
@@ -244,8 +280,9 @@ def time_steps(setup, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     per = {p: float(np.mean([ev[s][j].elapsed_time(ev[s][j + 1]) for s in range(steps)])) for j, p in enumerate(parts)}
-    step = float(np.mean([ev[s][0].elapsed_time(ev[s][-1]) for s in range(steps)]))
-    return step, wall, per
+    each = [ev[s][0].elapsed_time(ev[s][-1]) for s in range(steps)]
+    spread = {"median": float(np.median(each)), "min": float(np.min(each)), "max": float(np.max(each))}
+    return float(np.mean(each)), wall, per, spread
 
 
 def time_call(fn, reps, warmup=2):
@@ -509,7 +546,7 @@ def extras_16(args):
     U = inputs.gauge_field_device(cfg["L"], cfg["sigma"], cfg["seed_u"], "cuda")
     mr = Setup(cfg, U)
     autotune.autotune(mr.op, mr.n, N_SAP, N_MR, b=mr.b, x=mr.x)
-    step_ms, _, per = time_steps(mr, 10, 3)
+    step_ms, _, per, _ = time_steps(mr, 10, 3)
     mr.resid()
     res_max = float(mr.res.max().item())
     out = {"workload": workload_name(cfg), "step_ms": round(step_ms, 4),
@@ -666,6 +703,23 @@ def oracle_checks(cfg, host, fp16=None):
                               "sample": "32^3x64, test vector %d" % host["k"]}
     for v in acc.values():
         v["ok"] = bool(v["rel_err"] <= v["tol"])
+    # one thread on the 16^4 workload: SAP from x = 0 on one of its 20 vectors, scaled x20
+    log("oracle: one-thread SAP on 16^4")
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")  # the OpenMP runtime the oracle library runs on
+    L2 = C2["L"]
+    U2 = inputs.gauge_field(L2, C2["sigma"], C2["seed_u"])
+    A2 = oracle.clover(L2, U2, CSW, C2["m0"])
+    b2 = inputs.test_vectors(L2, 1, C2["seed_v"])
+    gomp.omp_set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.sap(L2, BLOCK, U2, A2, b2, N_SAP, N_MR)
+        t_one = (time.perf_counter() - t) * C2["n_tv"]
+    finally:
+        gomp.omp_set_num_threads(cores)
+    one = {"value": int(np.prod(L2)) * C2["n_tv"] * N_SAP / t_one, "unit": "site*RHS updates/s", "cores": 1,
+           "sample": "16^4, SAP 3x4 from x = 0 on 1 of 20 test vectors (scaled x20)"}
     total = t_sap + t_res + t_gs + t_dc
     cpu = {"value": V * n * N_SAP / total, "unit": "site*RHS updates/s", "cores": cores, "kind": "oracle",
            "sample": ("48^3x96 step: SAP + residual on 1 of %d test vectors (scaled x%d), block GS on %d of %d "
@@ -673,7 +727,8 @@ def oracle_checks(cfg, host, fp16=None):
                       "set-up (%.1f s) excluded; FP64 C, OpenMP"
                       % (n, n, len(host["gs_aggs"]), n_agg, len(host["dc"]), n_agg, t_clover)),
            "seconds_scaled": {"sap": round(t_sap, 2), "resid": round(t_res, 2), "gs": round(t_gs, 2),
-                              "dc": round(t_dc, 2)}}
+                              "dc": round(t_dc, 2)},
+           "one_thread_16x16x16x16_sap": one}
     return acc, cpu
 
 
@@ -736,6 +791,9 @@ def main():
     V = int(np.prod(L))
     log("generating the %s inputs on the device" % "x".join(map(str, L)))
     U = inputs.gauge_field_device(L, cfg["sigma"], cfg["seed_u"], "cuda")
+    plaq = average_plaquette(U, L)
+    torch.cuda.empty_cache()
+    log("average plaquette %.6f" % plaq)
     log("operator set-up")
     mr = Setup(cfg, U)
     if args.tiles:
@@ -746,11 +804,13 @@ def main():
         tiles = autotune.autotune(mr.op, n, N_SAP, N_MR, b=mr.b, x=mr.x)
     log("tiles: %s" % tiles)
     log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
-    step_ms, wall_ms, per = time_steps(mr, args.steps, args.warmup)
+    step_ms, wall_ms, per, spread = time_steps(mr, args.steps, args.warmup)
     assert int(mr.status.item()) == 0
     res = mr.res.cpu().numpy()
     log("step %.3f ms (wall %.3f): %s; residuals %.4f..%.4f" % (step_ms, wall_ms, per, res.min(), res.max()))
     value = V * n * N_SAP / (step_ms * 1e-3)
+    n_agg = V // int(np.prod(AGG))
+    plat = platform()
 
     # dominant kernel: the SAP half-sweep (2 * N_SAP launches per call, nothing else)
     n_launch = 2 * N_SAP
@@ -841,6 +901,14 @@ def main():
                    "aggregate": AGG, "parallelism": "single GPU",
                    "tiles": {"sap": tiles["sap"], "dirac": tiles["dirac"]}},
         "parts_ms": {k: round(float(x), 4) for k, x in per.items()},
+        "step_ms_spread": {k: round(x, 4) for k, x in spread.items()},
+        "rates": {"sap_d_equivalents_per_s": V * n * N_SAP * (N_MR + 1) / (per["sap"] * 1e-3),
+                  "gs_site_rhs_per_s": V * n / (per["gs"] * 1e-3),
+                  "gs_aggregates_per_s": n_agg / (per["gs"] * 1e-3),
+                  "dc_site_rhs_per_s": V * n / (per["dc"] * 1e-3),
+                  "dc_aggregates_per_s": n_agg / (per["dc"] * 1e-3)},
+        "average_plaquette": plaq,
+        "platform": plat,
         "residual_max": float(res.max()),
         "roofline": roof,
         "stencil_roofline": stencil,
