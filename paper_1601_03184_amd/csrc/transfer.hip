@@ -15,6 +15,8 @@
 // at ((i * 2 n_tv + c) * 2 + p) * ldc + k, ldc = n rounded up to a multiple of 4.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "launch.h"
 #include "stencil.h"
 
@@ -509,6 +511,11 @@ template <typename TD, int QN, int TK> __global__ void __launch_bounds__(256) k_
     f4 dr[2], di[2];
 #pragma unroll
     for (int tk = 0; tk < 2; ++tk) dr[tk] = di[tk] = f4{0.f, 0.f, 0.f, 0.f};
+    // binary16 D_c with two right-hand-side tiles: three real products per complex one (Gauss);
+    // the third accumulator pair fits in the registers of three wavefronts per SIMD there, not
+    // with FP32 D_c, whose slab takes twice the registers
+    constexpr bool G3 = std::is_same<TD, __half>::value;
+    f4 t3[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 
     float sgn0;
     const float *s0 = src_of(0, sgn0);
@@ -546,7 +553,16 @@ template <typename TD, int QN, int TK> __global__ void __launch_bounds__(256) k_
                         b[tk] = {0.f, 0.f};
                         if (col < N2 && k < a.n) b[tk] = yb[col * CS_YRS + k];
                     }
-                    if (TK == 2) {
+                    if (TK == 2 && G3) {
+                        // t1 = Ar Br (in dr), t2 = Ai Bi (in di), t3 = (Ar + Ai)(Br + Bi)
+                        const float as = ar + ai;
+                        dr[0] = mfma32(ar, b[0].x, dr[0]);
+                        di[0] = mfma32(ai, b[0].y, di[0]);
+                        t3[0] = mfma32(as, b[0].x + b[0].y, t3[0]);
+                        dr[1] = mfma32(ar, b[1].x, dr[1]);
+                        di[1] = mfma32(ai, b[1].y, di[1]);
+                        t3[1] = mfma32(as, b[1].x + b[1].y, t3[1]);
+                    } else if (TK == 2) {
                         dr[0] = mfma32(ar, b[0].x, dr[0]);
                         di[0] = mfma32(ar, b[0].y, di[0]);
                         dr[1] = mfma32(ar, b[1].x, dr[1]);
@@ -573,6 +589,14 @@ template <typename TD, int QN, int TK> __global__ void __launch_bounds__(256) k_
     if (TK == 1) {
         dr[0] += dr[1];
         di[0] += di[1];
+    } else if (G3) {
+        // Re = t1 - t2, Im = t3 - t1 - t2
+#pragma unroll
+        for (int tk = 0; tk < 2; ++tk) {
+            const f4 t1 = dr[tk], t2 = di[tk];
+            dr[tk] = t1 - t2;
+            di[tk] = t3[tk] - t1 - t2;
+        }
     }
     const float *o0 = a.y0 ? a.y0 + (size_t)i * N2 * 2 * a.ldc : nullptr;
     for (int tk = 0; tk < TK; ++tk)
