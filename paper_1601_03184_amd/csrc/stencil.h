@@ -169,50 +169,56 @@ __device__ inline void dirac_site_global(const KGeo &g, const Tf *__restrict__ l
 }
 
 // out += the hops of (D x)(site) whose neighbour lies outside the site's SAP block (the
-// part of the residual that couples a block to its neighbours); SKIP as above.
+// part of the residual that couples a block to its neighbours); SKIP as above.  A site lies on
+// at most one of the two faces of a direction unless its block is one site thick there, so
+// both faces' loads are issued in one round (each lane its own face's neighbour and link) and
+// the lanes on either face accumulate their hop; a one-site-thick block takes the backward
+// face in a second round.  Per lane the hops are added in the same order as face by face.
+template <int MU, typename Tc, typename Ts, typename Tf, typename Skip>
+__device__ inline void face_pair_global(const KGeo &g, const Tf *__restrict__ links, const Ts *__restrict__ x,
+                                        int grp, int t, int blk, int off, const int (&bc)[4], const int (&lc)[4],
+                                        Spinor<Tc> &out, Skip skip)
+{
+    const long ns = (long)blk * g.Vb + off;
+    const bool ff = lc[MU] + 1 == g.b[MU] && g.nb[MU] > 1;  // on the +MU face
+    const bool fb = lc[MU] == 0 && g.nb[MU] > 1;            // on the -MU face
+    if (ff || fb) {
+        const NbrSite n = ff ? nbr_fwd(g, MU, blk, off, bc, lc) : nbr_bwd(g, MU, blk, off, bc, lc);
+        if (!skip(n.blk)) {
+            Spinor<typename ChiType<Tc, Ts>::type> chi;
+            load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
+            Tc U[18];
+            load_link(links, g.V, MU, ff ? ns : (long)n.blk * g.Vb + n.off, U);
+            if (ff) hop_accumulate<MU, -1, false>(U, chi, out);
+            else hop_accumulate<MU, +1, true>(U, chi, out);
+        }
+    }
+    hop_fence(out);
+    if (ff && fb) {
+        const NbrSite n = nbr_bwd(g, MU, blk, off, bc, lc);
+        if (!skip(n.blk)) {
+            Spinor<typename ChiType<Tc, Ts>::type> chi;
+            load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
+            Tc U[18];
+            load_link(links, g.V, MU, (long)n.blk * g.Vb + n.off, U);
+            hop_accumulate<MU, +1, true>(U, chi, out);
+        }
+    }
+}
+
 template <typename Tc, typename Ts, typename Tf, typename Skip>
 __device__ inline void face_hops_global(const KGeo &g, const Tf *__restrict__ links, const Ts *__restrict__ x, int grp,
                                         int t, int blk, int off, const int (&bc)[4], const int (&lc)[4],
                                         Spinor<Tc> &out, Skip skip)
 {
-    const long ns = (long)blk * g.Vb + off;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        hop_fence(out);
-        // forward neighbour across the +mu face
-        if (lc[mu] + 1 == g.b[mu] && g.nb[mu] > 1) {
-            const NbrSite n = nbr_fwd(g, mu, blk, off, bc, lc);
-            if (!skip(n.blk)) {
-                Spinor<typename ChiType<Tc, Ts>::type> chi;
-                load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
-                Tc U[18];
-                load_link(links, g.V, mu, ns, U);
-                switch (mu) {
-                case 0: hop_accumulate<0, -1, false>(U, chi, out); break;
-                case 1: hop_accumulate<1, -1, false>(U, chi, out); break;
-                case 2: hop_accumulate<2, -1, false>(U, chi, out); break;
-                default: hop_accumulate<3, -1, false>(U, chi, out); break;
-                }
-            }
-        }
-        hop_fence(out);
-        // backward neighbour across the -mu face
-        if (lc[mu] == 0 && g.nb[mu] > 1) {
-            const NbrSite n = nbr_bwd(g, mu, blk, off, bc, lc);
-            if (!skip(n.blk)) {
-                Spinor<typename ChiType<Tc, Ts>::type> chi;
-                load_spinor<typename ChiType<Tc, Ts>::type>(g, x, grp, n.blk, n.off, t, chi);
-                Tc U[18];
-                load_link(links, g.V, mu, (long)n.blk * g.Vb + n.off, U);
-                switch (mu) {
-                case 0: hop_accumulate<0, +1, true>(U, chi, out); break;
-                case 1: hop_accumulate<1, +1, true>(U, chi, out); break;
-                case 2: hop_accumulate<2, +1, true>(U, chi, out); break;
-                default: hop_accumulate<3, +1, true>(U, chi, out); break;
-                }
-            }
-        }
-    }
+    hop_fence(out);
+    face_pair_global<0>(g, links, x, grp, t, blk, off, bc, lc, out, skip);
+    hop_fence(out);
+    face_pair_global<1>(g, links, x, grp, t, blk, off, bc, lc, out, skip);
+    hop_fence(out);
+    face_pair_global<2>(g, links, x, grp, t, blk, off, bc, lc, out, skip);
+    hop_fence(out);
+    face_pair_global<3>(g, links, x, grp, t, blk, off, bc, lc, out, skip);
     hop_fence(out);
 }
 
