@@ -19,6 +19,8 @@
 #include "launch.h"
 #include "stencil.h"
 
+#include <type_traits>
+
 namespace {
 
 template <typename Ts, typename Tc> struct SapArgs {
@@ -230,7 +232,19 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
         Spinor<Tc> r;
         if (a.mode != 0) {
             Spinor<Tc> bb;
-            if (a.sig_in) {
+            if constexpr (std::is_same<Ts, Tc>::value) {
+                // a visit that knows sigma, and the first visit of the second colour (x vanishes on
+                // the block, so D x is its face hops), through one call of the face hops
+                if (a.sig_in || a.mode == 1) {
+                    spinor_zero(r);
+                    const Tc *src = a.sig_in && a.inc ? (const Tc *)a.ecor : a.xr;
+                    face_hops_global<Tc>(g, a.links, src, grp, tt, blk, off, bc, lc, r, skip);
+                    load_spinor<Tc>(g, a.sig_in ? (const Tc *)a.sig : a.b, grp, blk, off, tt, bb);
+                } else {
+                    dirac_site_global<Tc>(g, a.links, a.clover, a.xr, grp, tt, blk, off, bc, lc, r, skip);
+                    load_spinor<Tc>(g, a.b, grp, blk, off, tt, bb);
+                }
+            } else if (a.sig_in) {
                 spinor_zero(r);
                 if (a.inc) face_hops_global<Tc>(g, a.links, (const Tc *)a.ecor, grp, tt, blk, off, bc, lc, r, skip);
                 else face_hops_global<Tc>(g, a.links, a.xr, grp, tt, blk, off, bc, lc, r, skip);
