@@ -188,10 +188,10 @@ __device__ inline void hop_accumulate(const T (&U)[18], const Spinor<Tx> &chi, S
     }
 }
 
-// out[6hf..6hf+5] = A_hf psi[6hf..6hf+5] for one chiral half hf of the site term, held
-// as 36 reals: 6 real diagonal entries, then the 15 upper entries (i<j, row-major) as
+// out[6hf..6hf+5] = A_hf psi[6hf..6hf+5] (ADD: += ) for one chiral half hf of the site term,
+// held as 36 reals: 6 real diagonal entries, then the 15 upper entries (i<j, row-major) as
 // (re, im); the lower triangle is their conjugate.
-template <int HF, typename T, typename Tx>
+template <int HF, bool ADD = false, typename T, typename Tx>
 __device__ inline void clover_half(const T (&cl)[36], const Spinor<Tx> &psi, Spinor<T> &out)
 {
     constexpr int o = 6 * HF;
@@ -210,8 +210,13 @@ __device__ inline void clover_half(const T (&cl)[36], const Spinor<Tx> &psi, Spi
             si += ur * T(psi.im[o + j]);
             si += ui * T(psi.re[o + j]);
         }
-        out.re[o + i] = sr;
-        out.im[o + i] = si;
+        if constexpr (ADD) {
+            out.re[o + i] += sr;
+            out.im[o + i] += si;
+        } else {
+            out.re[o + i] = sr;
+            out.im[o + i] = si;
+        }
     }
 }
 

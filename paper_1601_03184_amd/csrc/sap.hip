@@ -279,31 +279,49 @@ __device__ inline void sap_block(const SapArgs<Ts, Tc> &a, int blk, int tile, un
             const int ns = opaque_index(blk * g.Vb + off);
             // the clover term one chiral half at a time (it is block-diagonal in them): six
             // components of rho and 36 field values live instead of twelve and 72
-            {
-                Spinor<Tc> own;
-                Tc A[36];
-                lds_load_half<0, Tc>(rho, str, me, own);
-                load_clover_half<0>(a.clover, g.V, ns, A);
-                clover_half<0>(A, own, q);
-            }
-            hop_fence(q);
-            {
-                Spinor<Tc> own;
-                Tc A[36];
-                lds_load_half<1, Tc>(rho, str, me, own);
-                load_clover_half<1>(a.clover, g.V, ns, A);
-                clover_half<1>(A, own, q);
-            }
-            hop_fence(q);
+            auto clover_term = [&](auto add) {
+                {
+                    Spinor<Tc> own;
+                    Tc A[36];
+                    lds_load_half<0, Tc>(rho, str, me, own);
+                    load_clover_half<0>(a.clover, g.V, ns, A);
+                    clover_half<0, decltype(add)::value>(A, own, q);
+                }
+                hop_fence(q);
+                {
+                    Spinor<Tc> own;
+                    Tc A[36];
+                    lds_load_half<1, Tc>(rho, str, me, own);
+                    load_clover_half<1>(a.clover, g.V, ns, A);
+                    clover_half<1, decltype(add)::value>(A, own, q);
+                }
+                hop_fence(q);
+            };
             // (the LDS link indices are hidden like ns: the links are re-read in every step)
-            block_hops<0, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[0]) : 0, sb[0]);
-            hop_fence(q);
-            block_hops<1, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[1]) : 0, sb[1]);
-            hop_fence(q);
-            block_hops<2, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[2]) : 0, sb[2]);
-            hop_fence(q);
-            block_hops<3, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[3]) : 0, sb[3]);
-            hop_fence(q);
+            auto hops = [&]() {
+                block_hops<0, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[0]) : 0, sb[0]);
+                hop_fence(q);
+                block_hops<1, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[1]) : 0, sb[1]);
+                hop_fence(q);
+                block_hops<2, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[2]) : 0, sb[2]);
+                hop_fence(q);
+                block_hops<3, Tc, LL>(g, a.links, rho, T, ns, off, t, lcp, q, ul, LL ? opaque_index(cf[3]) : 0, sb[3]);
+                hop_fence(q);
+            };
+            // Every wavefront starts the step together after the barrier; the clover term is read
+            // from global memory, the hops from LDS.  Wavefronts 4-7 and 12-15 take the hops
+            // first and add the clover term last, so that some wavefronts compute while the
+            // others wait for the clover field (with the wavefronts placed on the four SIMDs in
+            // turn, each SIMD holds both kinds).
+            if ((wave >> 2) & 1) {
+                spinor_zero(q);
+                hop_fence(q);
+                hops();
+                clover_term(std::true_type{});
+            } else {
+                clover_term(std::false_type{});
+                hops();
+            }
 #pragma unroll
             for (int c = 0; c < 12; ++c) {
                 const P2 o = rho[c * str + me];
