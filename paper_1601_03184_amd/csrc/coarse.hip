@@ -38,6 +38,7 @@ template <typename Tq> struct CoarseArgs {
     int Va, n_agg, N;
     int sshift;          // log2 of the short length S
     long gsz;            // elements of one group of S right-hand sides
+    int part_major;      // work items part by part (all self blocks first), for short grids
     const int32_t *agg_sites;
     const uint32_t *blk_coords, *loc_coords;
     const Tq *Q;
@@ -222,8 +223,18 @@ __global__ void __launch_bounds__(NTHR) k_coarse(CoarseArgs<Tq> a, const Tc *__r
     float2 *Ws = Qs + CHS * 12 * QST;                               // [2][CHS][6][WST]
     // work item li = 5 i + d: aggregate i, part d (0: the self block; 1 + mu: the +mu face
     // block), so that the five parts of an aggregate are consecutive and a CU runs self and
-    // face workgroups side by side; items in contiguous runs per XCD
-    const int li = xcd_remap(blockIdx.x, gridDim.x), i = li / 5, d = li - 5 * i;
+    // face workgroups side by side; items in contiguous runs per XCD.  A grid of a few waves of
+    // resident workgroups takes the parts one after the other instead (the self blocks, the
+    // longest items, start first and do not end up as the tail), aggregates in XCD runs.
+    int i, d;
+    if (a.part_major) {
+        d = blockIdx.x / a.n_agg;
+        i = xcd_remap(blockIdx.x - d * a.n_agg, a.n_agg);
+    } else {
+        const int li = xcd_remap(blockIdx.x, gridDim.x);
+        i = li / 5;
+        d = li - 5 * i;
+    }
     const bool self = d == 0;
     const int mu = d - 1;
     const int nsites = self ? a.Va : a.Va / a.a[mu];
@@ -404,6 +415,8 @@ int coarse_dispatch(const mrhs_op *op, const Tc *links, const Tc *clover, const 
     a.sshift = 0;
     while ((1 << a.sshift) < op->k.S) ++a.sshift;
     a.gsz = (long)op->k.nblk * 24 * op->k.Vb * op->k.S;
+    // up to about eight waves of resident workgroups (two per CU): part by part
+    a.part_major = op->n_agg * 5 <= 4096;
     a.agg_sites = op->agg_sites;
     a.blk_coords = op->blk_coords;
     a.loc_coords = op->loc_coords;
